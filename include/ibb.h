@@ -1,0 +1,159 @@
+/*
+ * ibb.h -- rigorous interval branch-and-bound for square polynomial systems on
+ * a box, with the Hansen-Sengupta contraction, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Lin & Chen, "An efficient algorithm for global interval solution of
+ * nonlinear algebraic equations and its GPGPU implementation" (arXiv
+ * 1802.00330).  Problem statement and outputs: Sec. 3.1, Alg. 1 (input: the
+ * equations, the variable ranges, the desired width; output: the boxes that may
+ * hold solutions).  Per box: interval evaluation and the exclusion test
+ * (Sec. 2.2, Def. 1-2; Alg. 2), the Hansen-Sengupta step (Sec. 2.3 eq 17-22;
+ * Alg. 3-4) and bisection (Alg. 2).  A box whose contraction lands strictly
+ * inside it holds exactly one root (Alg. 3, second output) and is tagged
+ * IBB_UNIQUE.
+ *
+ * Conventions for every entry point:
+ *  - All pointers are plain host pointers unless the name starts with d_
+ *    (device memory on the context's GPU).  Inputs are borrowed for the call;
+ *    for *_async calls, until the work enqueued on the stream has completed.
+ *  - The library never frees memory it did not allocate.  A context owns its
+ *    internal buffers; one context per host thread.
+ *  - Every call returns an int status (IBB_OK or a negative IBB_ERR_*); no C++
+ *    exception crosses this interface.  On error, outputs are unspecified
+ *    except where stated.
+ *  - Results are deterministic: each box's fate depends only on the box, so the
+ *    sorted output list and the counters do not depend on scheduling.
+ */
+#ifndef IBB_H
+#define IBB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define IBB_OK 0
+#define IBB_ERR_INVALID_ARG (-1)     /* malformed system, box or parameters            */
+#define IBB_ERR_BUDGET (-2)          /* the search tree has more than max_boxes nodes  */
+#define IBB_ERR_OUTPUT_CAPACITY (-3) /* more boxes than `cap`; *n_out = required count */
+#define IBB_ERR_QUEUE_OVERFLOW (-4)  /* a tree level exceeded the frontier capacity    */
+#define IBB_ERR_NO_MEMORY (-5)       /* device or host allocation failed               */
+#define IBB_ERR_DEVICE (-6)          /* a HIP runtime call failed                      */
+#define IBB_ERR_UNSUPPORTED (-7)     /* valid request outside this build's limits      */
+#define IBB_ERR_TIMEOUT (-8)         /* a device-side wait exceeded its time limit     */
+
+/* ---- limits ---- */
+#define IBB_MAX_N 16      /* equations = variables                        */
+#define IBB_MAX_DEG 8     /* total degree of a term                       */
+#define IBB_MAX_TERMS 4096/* terms per system                             */
+
+/* ---- tags of output boxes ---- */
+#define IBB_UNDECIDED 0   /* may hold roots (width reached or split exhausted) */
+#define IBB_UNIQUE 1      /* holds exactly one root (Alg. 3, second output)    */
+
+/* ---- bisection ---- */
+#define IBB_SPLIT_WIDEST 0 /* bisect the widest coordinate (first on ties) */
+#define IBB_SPLIT_ALL 1    /* bisect every coordinate: 2^n children (Alg. 2) */
+
+/* A square polynomial system in sparse monomial form (Sec. 2.1).
+ * Equation i owns terms term_off[i] .. term_off[i+1]-1, in the order given;
+ * term t is coef[t] * prod_k x_k^expo[t*n + k].  Requirements: 1 <= n <= 16,
+ * every equation has >= 1 term, finite |coef| <= 2^40, total degree <= 8,
+ * at most IBB_MAX_TERMS terms. */
+typedef struct {
+  int32_t n;
+  const int32_t* term_off; /* [n+1], term_off[0] = 0, strictly increasing */
+  const uint8_t* expo;     /* [T*n], T = term_off[n]                      */
+  const double* coef;      /* [T]                                          */
+} ibb_system;
+
+/* Search parameters (Alg. 1 inputs plus the contraction policy). */
+typedef struct {
+  double tol;              /* emit a box once every coordinate is <= tol wide (> 0)     */
+  int64_t max_boxes;       /* budget on the number of tree nodes processed (>= 1)       */
+  int32_t split_mode;      /* IBB_SPLIT_WIDEST or IBB_SPLIT_ALL                          */
+  int32_t max_recontract;  /* consecutive re-contractions before bisecting (>= 1; 16)   */
+  double recontract_ratio; /* re-contract when the width shrank to <= ratio * width (0.5) */
+  double hs_max_width;     /* skip the contraction on boxes wider than this (+inf)       */
+} ibb_params;
+
+/* Counters of the search tree (identical on every run and on the CPU oracle). */
+typedef struct {
+  int64_t processed;         /* tree nodes stepped                               */
+  int64_t excluded_eval;     /* discarded by the exclusion test (Def. 2)         */
+  int64_t excluded_hs;       /* discarded by an empty contraction (Alg. 3)       */
+  int64_t hs_skipped;        /* contraction skipped (unusable preconditioner)   */
+  int64_t recontracted;      /* re-queued after a strong contraction            */
+  int64_t bisected;          /* split into children                              */
+  int64_t emitted_unique;    /* output boxes tagged IBB_UNIQUE                   */
+  int64_t emitted_undecided; /* output boxes tagged IBB_UNDECIDED                */
+  int64_t levels;            /* depth of the tree (levels processed)             */
+  int64_t max_frontier;      /* widest tree level                                */
+  double kernel_ms;          /* device time of the search (host-timed calls)     */
+} ibb_stats;
+
+typedef struct ibb_ctx ibb_ctx;
+
+/* Create a context on HIP device `device` (loads the kernels, queries the
+ * device).  Returns IBB_OK and *out, or IBB_ERR_DEVICE. */
+int ibb_ctx_create(int device, ibb_ctx** out);
+void ibb_ctx_destroy(ibb_ctx* ctx);
+
+/* Static description of a status code. */
+const char* ibb_strerror(int status);
+
+/* Default parameters: tol 1e-8, max_boxes 10^8, widest split, 16, 0.5, +inf. */
+void ibb_params_default(ibb_params* p);
+
+/* Solve one system on the box [lo, hi] (host arrays of n doubles).
+ * Outputs (host, caller-allocated): out_lo/out_hi [cap*n] row-major boxes,
+ * out_tag [cap]; *n_out = number of boxes.  The list is sorted
+ * lexicographically by (lo_0..lo_{n-1}, hi_0..hi_{n-1}, tag) with -0 written
+ * as +0.  If the list holds more than `cap` boxes the call returns
+ * IBB_ERR_OUTPUT_CAPACITY and *n_out is the required count.  `stats` may be
+ * NULL.  Synchronous; device memory comes from the context. */
+int ibb_solve(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const double* hi,
+              const ibb_params* params, double* out_lo, double* out_hi, uint8_t* out_tag,
+              int64_t cap, int64_t* n_out, ibb_stats* stats);
+
+/* Device workspace (bytes) that ibb_solve_async needs for a system with n
+ * variables, a frontier of `frontier_cap` boxes per tree level and `out_cap`
+ * output boxes. */
+size_t ibb_workspace_size(int32_t n, int64_t frontier_cap, int64_t out_cap);
+
+/* Enqueue a solve on `stream` (a hipStream_t, NULL = default stream) using
+ * caller-provided device memory: d_ws (>= ibb_workspace_size bytes, 256-byte
+ * aligned), outputs d_out_lo/d_out_hi [out_cap*n], d_out_tag [out_cap] and
+ * d_info [16] int64 written when the stream reaches the end of the solve:
+ *   d_info[0] status, [1] number of output boxes (may exceed out_cap, then the
+ *   status is IBB_ERR_OUTPUT_CAPACITY), [2..11] the ibb_stats counters in
+ *   order (processed .. max_frontier).
+ * The host inputs are copied before the call returns.  Returns IBB_OK when the
+ * work was enqueued; argument errors are returned directly. */
+int ibb_solve_async(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const double* hi,
+                    const ibb_params* params, void* d_ws, size_t ws_bytes, int64_t frontier_cap,
+                    int64_t out_cap, double* d_out_lo, double* d_out_hi, uint8_t* d_out_tag,
+                    int64_t* d_info, void* stream);
+
+/* Per-level frontier sizes of the most recent ibb_solve on this context
+ * (level 0 = the initial box): copies min(count, cap) values, returns the
+ * number of levels.  The boxes kept by the exclusion test at a level are the
+ * paper's per-round counts (Tables 1, 4, 7) when split_mode = IBB_SPLIT_ALL
+ * and the contraction is off (hs_max_width = 0). */
+int64_t ibb_last_level_sizes(ibb_ctx* ctx, int64_t* sizes, int64_t cap);
+
+/* Diagnostics: apply one rounding primitive of the device arithmetic to n
+ * operand pairs (host arrays) -- op 0..7 = rd/ru of + - * /, 8 = narrowing to
+ * single precision (round to nearest, result widened), 9 = midpoint
+ * rd(rd(a+b)*0.5), 10 = single-precision a*b, 11 = single-precision a/b.
+ * For checking the device primitives against exact arithmetic. */
+int ibb_selftest_ops(ibb_ctx* ctx, int32_t op, int64_t n, const double* a, const double* b,
+                     double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IBB_H */

@@ -1,0 +1,243 @@
+"""Python binding of the MI355X interval branch-and-bound library (libibb.so).
+
+Argument marshalling only: every step of the search runs in the library's HIP
+kernels.  PyTorch supplies device memory and the stream for ``solve``; the
+names ``ibb_*`` mirror the C entry points of ``include/ibb.h``.
+
+There is no fallback: if ``libibb.so`` has not been built, or no GPU is
+visible, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libibb.so")
+
+OK = 0
+ERR_INVALID_ARG, ERR_BUDGET, ERR_OUTPUT_CAPACITY, ERR_QUEUE_OVERFLOW = -1, -2, -3, -4
+ERR_NO_MEMORY, ERR_DEVICE, ERR_UNSUPPORTED, ERR_TIMEOUT = -5, -6, -7, -8
+SPLIT_WIDEST, SPLIT_ALL = 0, 1
+UNDECIDED, UNIQUE = 0, 1
+MAX_N = 16
+
+STATS_FIELDS = ("processed", "excluded_eval", "excluded_hs", "hs_skipped", "recontracted",
+                "bisected", "emitted_unique", "emitted_undecided")
+
+EXPORTS = ("ibb_ctx_create", "ibb_ctx_destroy", "ibb_strerror", "ibb_params_default", "ibb_solve",
+           "ibb_workspace_size", "ibb_solve_async", "ibb_last_level_sizes", "ibb_selftest_ops")
+
+
+class IbbSystem(C.Structure):
+    _fields_ = [("n", C.c_int32), ("term_off", C.c_void_p), ("expo", C.c_void_p), ("coef", C.c_void_p)]
+
+
+class IbbParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_boxes", C.c_int64), ("split_mode", C.c_int32),
+                ("max_recontract", C.c_int32), ("recontract_ratio", C.c_double),
+                ("hs_max_width", C.c_double)]
+
+
+class IbbStats(C.Structure):
+    _fields_ = [(f, C.c_int64) for f in STATS_FIELDS] + [("levels", C.c_int64), ("max_frontier", C.c_int64),
+                                                        ("kernel_ms", C.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libibb.so and declare the C signatures (raises if missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run paper_1802_00330_amd/build.py (hipcc, gfx950)")
+    L = C.CDLL(path)
+    p, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.ibb_ctx_create.restype, L.ibb_ctx_create.argtypes = C.c_int, [C.c_int, C.POINTER(C.c_void_p)]
+    L.ibb_ctx_destroy.restype, L.ibb_ctx_destroy.argtypes = None, [p]
+    L.ibb_strerror.restype, L.ibb_strerror.argtypes = C.c_char_p, [C.c_int]
+    L.ibb_params_default.restype, L.ibb_params_default.argtypes = None, [C.POINTER(IbbParams)]
+    L.ibb_solve.restype = C.c_int
+    L.ibb_solve.argtypes = [p, C.POINTER(IbbSystem), p, p, C.POINTER(IbbParams), p, p, p, i64,
+                            C.POINTER(C.c_int64), C.POINTER(IbbStats)]
+    L.ibb_workspace_size.restype, L.ibb_workspace_size.argtypes = C.c_size_t, [i32, i64, i64]
+    L.ibb_solve_async.restype = C.c_int
+    L.ibb_solve_async.argtypes = [p, C.POINTER(IbbSystem), p, p, C.POINTER(IbbParams), p, C.c_size_t, i64, i64,
+                                  p, p, p, p, p]
+    L.ibb_last_level_sizes.restype, L.ibb_last_level_sizes.argtypes = i64, [p, p, i64]
+    L.ibb_selftest_ops.restype, L.ibb_selftest_ops.argtypes = C.c_int, [p, i32, i64, p, p, p]
+    _lib = L
+    return L
+
+
+def ibb_strerror(status: int) -> str:
+    return load_library().ibb_strerror(int(status)).decode()
+
+
+class Context:
+    """An ibb_ctx on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        L = load_library()
+        h = C.c_void_p()
+        st = L.ibb_ctx_create(int(device), C.byref(h))
+        if st != OK:
+            raise RuntimeError(f"ibb_ctx_create({device}) failed: {ibb_strerror(st)}")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            load_library().ibb_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ibb_ctx_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class _SysRef:
+    """Keeps the numpy arrays of a system alive for the duration of a call."""
+
+    def __init__(self, s):
+        self.term_off = np.ascontiguousarray(s.term_off, dtype=np.int32)
+        self.expo = np.ascontiguousarray(s.expo, dtype=np.uint8)
+        self.coef = np.ascontiguousarray(s.coef, dtype=np.float64)
+        self.c = IbbSystem(int(s.n), self.term_off.ctypes.data, self.expo.ctypes.data, self.coef.ctypes.data)
+
+
+def make_params(tol: float, max_boxes: int = 100_000_000, split_mode: int = SPLIT_WIDEST,
+                max_recontract: int = 16, recontract_ratio: float = 0.5,
+                hs_max_width: float = float("inf")) -> IbbParams:
+    return IbbParams(float(tol), int(max_boxes), int(split_mode), int(max_recontract),
+                     float(recontract_ratio), float(hs_max_width))
+
+
+@dataclass
+class Result:
+    status: int
+    lo: np.ndarray   # [m, n]
+    hi: np.ndarray   # [m, n]
+    tag: np.ndarray  # [m] uint8
+    stats: dict
+    levels: int = 0
+    max_frontier: int = 0
+    kernel_ms: float = 0.0
+
+
+def ibb_solve(ctx: Context, s, params: IbbParams, lo=None, hi=None, cap: int = 1 << 14) -> Result:
+    """Host-pointer entry point (the library allocates device memory)."""
+    L = load_library()
+    ref = _SysRef(s)
+    lo = np.ascontiguousarray(s.lo if lo is None else lo, dtype=np.float64)
+    hi = np.ascontiguousarray(s.hi if hi is None else hi, dtype=np.float64)
+    while True:
+        olo = np.zeros((cap, s.n))
+        ohi = np.zeros((cap, s.n))
+        otag = np.zeros(cap, dtype=np.uint8)
+        nout = C.c_int64(0)
+        st_ = IbbStats()
+        st = L.ibb_solve(ctx.handle, C.byref(ref.c), _ptr(lo), _ptr(hi), C.byref(params), _ptr(olo), _ptr(ohi),
+                         _ptr(otag), int(cap), C.byref(nout), C.byref(st_))
+        if st == ERR_OUTPUT_CAPACITY and nout.value > cap:
+            cap = int(nout.value)
+            continue
+        m = int(nout.value) if st == OK else 0
+        stats = {f: int(getattr(st_, f)) for f in STATS_FIELDS}
+        return Result(st, olo[:m].copy(), ohi[:m].copy(), otag[:m].copy(), stats, int(st_.levels),
+                      int(st_.max_frontier), float(st_.kernel_ms))
+
+
+def ibb_last_level_sizes(ctx: Context, cap: int = 1 << 16) -> np.ndarray:
+    buf = np.zeros(cap, dtype=np.int64)
+    m = load_library().ibb_last_level_sizes(ctx.handle, _ptr(buf), int(cap))
+    return buf[:min(m, cap)].copy()
+
+
+def ibb_workspace_size(n: int, frontier_cap: int, out_cap: int) -> int:
+    return int(load_library().ibb_workspace_size(int(n), int(frontier_cap), int(out_cap)))
+
+
+def ibb_solve_async(ctx: Context, s, params: IbbParams, ws, frontier_cap: int, out_cap: int,
+                    out_lo, out_hi, out_tag, info, stream=None, lo=None, hi=None) -> int:
+    """Device-pointer entry point: ws/out_*/info are torch CUDA tensors (or
+    integer device addresses); the solve is enqueued on `stream`."""
+    import torch
+
+    def addr(t):
+        return t.data_ptr() if isinstance(t, torch.Tensor) else int(t)
+
+    ref = _SysRef(s)
+    lo = np.ascontiguousarray(s.lo if lo is None else lo, dtype=np.float64)
+    hi = np.ascontiguousarray(s.hi if hi is None else hi, dtype=np.float64)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    nbytes = ws.numel() * ws.element_size() if isinstance(ws, torch.Tensor) else ibb_workspace_size(
+        s.n, frontier_cap, out_cap)
+    return load_library().ibb_solve_async(ctx.handle, C.byref(ref.c), _ptr(lo), _ptr(hi), C.byref(params),
+                                          C.c_void_p(addr(ws)), C.c_size_t(nbytes), int(frontier_cap),
+                                          int(out_cap), C.c_void_p(addr(out_lo)), C.c_void_p(addr(out_hi)),
+                                          C.c_void_p(addr(out_tag)), C.c_void_p(addr(info)),
+                                          C.c_void_p(sh))
+
+
+def solve(ctx: Context, s, tol: Optional[float] = None, frontier_cap: int = 1 << 20, out_cap: int = 1 << 12,
+          device: str = "cuda", stream=None, **kw) -> Result:
+    """Solve one system with torch-allocated device memory on a torch stream;
+    grows the frontier / output buffers and retries on capacity errors."""
+    import torch
+
+    params = make_params(s.tol if tol is None else tol, **kw)
+    while True:
+        nbytes = ibb_workspace_size(s.n, frontier_cap, out_cap)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        olo = torch.empty(max(out_cap, 1) * s.n, dtype=torch.float64, device=device)
+        ohi = torch.empty_like(olo)
+        otag = torch.empty(max(out_cap, 1), dtype=torch.uint8, device=device)
+        info = torch.zeros(16, dtype=torch.int64, device=device)
+        st = ibb_solve_async(ctx, s, params, ws, frontier_cap, out_cap, olo, ohi, otag, info, stream=stream)
+        if st != OK:
+            return Result(st, np.zeros((0, s.n)), np.zeros((0, s.n)), np.zeros(0, np.uint8), {})
+        (stream or torch.cuda.current_stream()).synchronize()
+        inf = info.cpu().numpy()
+        status = int(inf[0])
+        if status == ERR_QUEUE_OVERFLOW:
+            frontier_cap *= 4
+            continue
+        if status == ERR_OUTPUT_CAPACITY:
+            out_cap = int(inf[1])
+            continue
+        stats = dict(zip(STATS_FIELDS, (int(v) for v in inf[2:10])))
+        m = int(inf[1]) if status == OK else 0
+        lo = olo[: m * s.n].view(m, s.n).cpu().numpy() if m else np.zeros((0, s.n))
+        hi = ohi[: m * s.n].view(m, s.n).cpu().numpy() if m else np.zeros((0, s.n))
+        tag = otag[:m].cpu().numpy() if m else np.zeros(0, np.uint8)
+        return Result(status, lo, hi, tag, stats, int(inf[10]), int(inf[11]))
+
+
+def ibb_selftest_ops(ctx: Context, op: int, a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    out = np.zeros_like(a)
+    st = load_library().ibb_selftest_ops(ctx.handle, int(op), int(a.size), _ptr(a), _ptr(b), _ptr(out))
+    if st != OK:
+        raise RuntimeError(f"ibb_selftest_ops: {ibb_strerror(st)}")
+    return out

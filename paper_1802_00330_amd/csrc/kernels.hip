@@ -1,0 +1,892 @@
+// kernels.hip -- the per-box branch-and-bound step on gfx950.
+//
+// One persistent cooperative launch runs the whole search tree level by level
+// (Alg. 1: the round sets M_0, M_1, ...).  A level's boxes sit in a device
+// frontier; waves claim tiles of boxes with one atomic, step them, and append
+// children / output boxes with one atomic per wave after a ballot + prefix-sum
+// compaction.  A grid barrier separates levels.
+//
+// Inside a wave, a box is owned by a group of G lanes (G = next power of two
+// >= n): lane r owns row r -- equation r for F(X) and J(X), the row of the
+// single-precision LU it holds, and, after the LU, the row of the
+// preconditioner at its logical pivot position.
+#include <hip/hip_runtime.h>
+
+#include "interval.hpp"
+#include "layout.hpp"
+
+namespace ibb {
+
+// ---------------------------------------------------------------------------
+// Wave-level helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t group_bits(uint64_t ballot, int g) {
+  constexpr uint64_t gm = (G >= 64) ? ~0ull : ((1ull << G) - 1ull);
+  return (ballot >> (g * G)) & gm;
+}
+
+template <int G>
+__device__ __forceinline__ double group_max(double x) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, G));
+  return x;
+}
+
+// Largest v; ties to the smallest key.  Every lane of the group gets the winner.
+template <int G>
+__device__ __forceinline__ void group_argmax(double& v, int& key, int& who) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    double ov = __shfl_xor(v, o, G);
+    int ok = __shfl_xor(key, o, G);
+    int ow = __shfl_xor(who, o, G);
+    if (ov > v || (ov == v && ok < key)) {
+      v = ov;
+      key = ok;
+      who = ow;
+    }
+  }
+}
+
+// Inclusive prefix sum over the 64 lanes of the wave.
+__device__ __forceinline__ unsigned wave_inclusive_sum(unsigned x) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    unsigned y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// The compiled system, staged once per workgroup in LDS.
+// ---------------------------------------------------------------------------
+struct LTable {
+  int n;
+  const int* eq_off;
+  const int* der_off;
+  const uint32_t* jnz;
+  const double* coef;
+  const uint64_t* fac;
+  const iv* dco;  // [R(e c), -R(-e c)]: the derivative coefficient, enclosed
+  const uint64_t* dfac;
+};
+
+// All threads of the block cooperate; requires the FP64 round-down mode.
+__device__ LTable stage_table(const uint64_t* blob, char* lds) {
+  const SysDesc* d = reinterpret_cast<const SysDesc*>(blob);
+  const int n = d->n, T = d->T, TD = d->TD;
+  char* p = lds;
+  int* eq_off = reinterpret_cast<int*>(p);
+  p += align16(sizeof(int) * (n + 1));
+  int* der_off = reinterpret_cast<int*>(p);
+  p += align16(sizeof(int) * (n * n + 1));
+  uint32_t* jnz = reinterpret_cast<uint32_t*>(p);
+  p += align16(sizeof(uint32_t) * kMaxN);
+  double* coef = reinterpret_cast<double*>(p);
+  p += align16(sizeof(double) * T);
+  uint64_t* fac = reinterpret_cast<uint64_t*>(p);
+  p += align16(sizeof(uint64_t) * T);
+  iv* dco = reinterpret_cast<iv*>(p);
+  p += align16(sizeof(iv) * TD);
+  uint64_t* dfac = reinterpret_cast<uint64_t*>(p);
+
+  const int* g_eq = reinterpret_cast<const int*>(blob + d->eq_off_w);
+  const int* g_der = reinterpret_cast<const int*>(blob + d->der_off_w);
+  const double* g_coef = reinterpret_cast<const double*>(blob + d->coef_w);
+  const uint64_t* g_fac = blob + d->fac_w;
+  const double* g_dcoef = reinterpret_cast<const double*>(blob + d->dcoef_w);
+  const uint32_t* g_dmult = reinterpret_cast<const uint32_t*>(blob + d->dmult_w);
+  const uint64_t* g_dfac = blob + d->dfac_w;
+  for (int i = threadIdx.x; i <= n; i += blockDim.x) eq_off[i] = g_eq[i];
+  for (int i = threadIdx.x; i <= n * n; i += blockDim.x) der_off[i] = g_der[i];
+  for (int i = threadIdx.x; i < kMaxN; i += blockDim.x) jnz[i] = d->jnz[i];
+  for (int i = threadIdx.x; i < T; i += blockDim.x) {
+    coef[i] = g_coef[i];
+    fac[i] = g_fac[i];
+  }
+  for (int i = threadIdx.x; i < TD; i += blockDim.x) {
+    // derivative coefficient e_k * c, enclosed (both bounds rounded outward)
+    double e = (double)g_dmult[i];
+    double c = g_dcoef[i];
+    dco[i] = iv{rmul(e, c), rmul_neg(e, c)};
+    dfac[i] = g_dfac[i];
+  }
+  return LTable{n, eq_off, der_off, jnz, coef, fac, dco, dfac};
+}
+
+// ---------------------------------------------------------------------------
+// Interval evaluation (Def. 1): monomials as products of powers, variables
+// ascending, coefficient last; equations as sums of terms in stored order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ iv eval_monomial(uint64_t f, const iv* X) {
+  iv m = ipow(X[f & 0xF], (int)((f >> 4) & 0xF));
+  f >>= 8;
+  while (f & 0xF0) {
+    m = imul(m, ipow(X[f & 0xF], (int)((f >> 4) & 0xF)));
+    f >>= 8;
+  }
+  return m;
+}
+
+__device__ __forceinline__ iv eval_equation(const LTable& t, int i, const iv* X) {
+  const int a = t.eq_off[i], b = t.eq_off[i + 1];
+  iv acc{0.0, 0.0};
+  for (int q = a; q < b; ++q) {
+    const uint64_t f = t.fac[q];
+    const double c = t.coef[q];
+    iv v = f ? pmul(c, eval_monomial(f, X)) : point_iv(c);
+    acc = (q == a) ? v : iadd(acc, v);
+  }
+  return acc;
+}
+
+// d f_i / d x_k over X (Alg. 3, first step); [0,0] without terms.
+__device__ __forceinline__ iv eval_partial(const LTable& t, int i, int k, const iv* X) {
+  const int a = t.der_off[i * t.n + k], b = t.der_off[i * t.n + k + 1];
+  iv acc{0.0, -0.0};
+  for (int q = a; q < b; ++q) {
+    const uint64_t f = t.dfac[q];
+    const iv c = t.dco[q];
+    iv v = f ? imul(c, eval_monomial(f, X)) : c;
+    acc = (q == a) ? v : iadd(acc, v);
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Per-wave scratch in LDS for the W = 64/G boxes of a tile.
+// ---------------------------------------------------------------------------
+template <int G>
+struct Scratch {
+  static constexpr int W = 64 / G;
+  iv X[W][G];      // current box
+  iv Xn[W][G];     // contracted box
+  iv D[W][G];      // X - mid X, then X' - mid X as the sweep advances
+  iv Fc[W][G];     // F at the expansion point
+  iv Xc[W][G];     // expansion point as degenerate intervals
+  iv J[W][G][G];   // interval Jacobian, row = equation
+  float row[W][G]; // broadcast buffer of the single-precision solver
+};
+
+// Narrowing of the midpoint of J to single precision, round to nearest.  The
+// conversion instruction takes its rounding from the FP32 field of MODE,
+// which the kernels leave at round-to-nearest-even.
+__device__ __forceinline__ float narrow_rn(double x) { return (float)x; }
+
+struct StepCounters {
+  unsigned long long s[8];
+};
+
+enum : int { kProcessed = 0, kExclEval, kExclHs, kHsSkipped, kRecontract, kBisected, kEmitU, kEmitUnd };
+
+// Extended division N / P (eq 10) followed by Y = x - Q, the intersection
+// with X_i and the hull of the pieces (eq 21-22).  Returns false when the
+// intersection is empty.  `inside` reports Y strictly inside X_i with Q one
+// bounded interval (the uniqueness condition of Alg. 3).
+__device__ __noinline__ bool gs_component(iv N, iv P, double xc, iv Xi, iv& Xn, bool& inside) {
+  const double na = N.lo, nb = -N.nhi;
+  const double pc = P.lo, pd = -P.nhi;
+  const double INF = __builtin_huge_val();
+  int npieces = 1;
+  double q0l = 0.0, q0h = 0.0, q1l = 0.0, q1h = 0.0;
+  bool bounded = false;
+  if (pc > 0.0 || pd < 0.0) {
+    // ordinary quotient: the extreme endpoint quotients, chosen by sign class
+    double ln, ld, hn, hd;
+    if (pc > 0.0) {
+      if (na >= 0.0) { ln = na; ld = pd; hn = nb; hd = pc; }
+      else if (nb <= 0.0) { ln = na; ld = pc; hn = nb; hd = pd; }
+      else { ln = na; ld = pc; hn = nb; hd = pc; }
+    } else {
+      if (na >= 0.0) { ln = nb; ld = pd; hn = na; hd = pc; }
+      else if (nb <= 0.0) { ln = nb; ld = pc; hn = na; hd = pd; }
+      else { ln = nb; ld = pd; hn = na; hd = pd; }
+    }
+    q0l = rd_div(ln, ld);
+    q0h = ru_div(hn, hd);
+    bounded = isfinite(q0l) && isfinite(q0h);
+  } else if (na <= 0.0 && nb >= 0.0) {
+    q0l = -INF;
+    q0h = INF;
+  } else if (pc == 0.0 && pd == 0.0) {
+    npieces = 0;
+  } else if (nb < 0.0) {
+    if (pc == 0.0) { q0l = -INF; q0h = ru_div(nb, pd); }
+    else if (pd == 0.0) { q0l = rd_div(nb, pc); q0h = INF; }
+    else { npieces = 2; q0l = -INF; q0h = ru_div(nb, pd); q1l = rd_div(nb, pc); q1h = INF; }
+  } else {
+    if (pc == 0.0) { q0l = rd_div(na, pd); q0h = INF; }
+    else if (pd == 0.0) { q0l = -INF; q0h = ru_div(na, pc); }
+    else { npieces = 2; q0l = -INF; q0h = ru_div(na, pc); q1l = rd_div(na, pd); q1h = INF; }
+  }
+  bool any = false;
+  double lo = 0.0, nhi = 0.0;
+  inside = (npieces == 1) && bounded;
+  for (int q = 0; q < npieces; ++q) {
+    const double ql = q ? q1l : q0l, qh = q ? q1h : q0h;
+    const iv Yq = isub(point_iv(xc), make_iv(ql, qh));
+    if (npieces == 1) inside = inside && (Xi.lo < Yq.lo) && (Yq.nhi > Xi.nhi);
+    const double il = fmax(Yq.lo, Xi.lo), inh = fmax(Yq.nhi, Xi.nhi);
+    if (!(il > -inh)) {
+      if (!any) {
+        lo = il;
+        nhi = inh;
+        any = true;
+      } else {
+        lo = fmin(lo, il);
+        nhi = fmin(nhi, inh);
+      }
+    }
+  }
+  Xn = iv{lo, nhi};
+  return any;
+}
+
+// One tile: boxes [base, base + W) of the current level (those < cnt).
+template <int G>
+__device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, long long base,
+                          long long cnt, int cur, unsigned long long* next_count,
+                          StepCounters& sc) {
+  const int lane = __lane_id();
+  const int g = lane / G;
+  const int r = lane % G;
+  const int n = T.n;
+  const long long idx = base + g;
+  const bool valid = idx < cnt;
+  const bool row_ok = r < n;
+
+  // ---- load the box and its record
+  uint32_t meta = 0;
+  if (valid) {
+    if (row_ok) {
+      const double* src = a.front[cur] + ((size_t)idx * G + r) * 2;
+      S.X[g][r] = iv{src[0], src[1]};
+    }
+    meta = a.meta[cur][idx];
+  }
+  const bool proven = meta & 1u;
+  const int rc = (int)((meta >> 8) & 0xFF);
+  wave_lds_sync();
+
+  // ---- exclusion test (Def. 2): some F_i(X) excludes 0
+  bool excl_row = false;
+  if (valid && !proven && row_ok) {
+    const iv f = eval_equation(T, r, S.X[g]);
+    excl_row = f.lo > 0.0 || f.nhi > 0.0;
+  }
+  const bool excluded = group_bits<G>(__ballot(excl_row), g) != 0;
+  const bool active = valid && !excluded;
+
+  // ---- width of X
+  const double w = group_max<G>((active && row_ok) ? iwidth(S.X[g][r]) : 0.0);
+  const bool do_hs = active && !(w > a.hs_max_width);
+
+  bool hs_empty = false, hs_unique = false, run = false;
+  if (__ballot(do_hs) != 0) {
+    // H1, H8: expansion point x = mid X and X - x
+    if (do_hs && row_ok) {
+      const iv x = S.X[g][r];
+      const double m = imid(x);
+      S.Xc[g][r] = point_iv(m);
+      S.D[g][r] = isub(x, point_iv(m));
+    }
+    wave_lds_sync();
+    // H2, H3: row r of J(X); F_r at the degenerate box [x, x]
+    if (do_hs && row_ok) {
+      for (int k = 0; k < n; ++k) S.J[g][r][k] = eval_partial(T, r, k, S.X[g]);
+      S.Fc[g][r] = eval_equation(T, r, S.Xc[g]);
+    }
+    wave_lds_sync();
+    // H4: single-precision mid J, row r
+    float M[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) M[k] = (do_hs && row_ok && k < n) ? narrow_rn(imid(S.J[g][r][k])) : 0.0f;
+
+    // H5: LU with partial pivoting across the lanes of the group; pos is the
+    // logical row this lane's data occupies after the row exchanges.
+    int pos = r;
+    bool bad = false, zero_pivot = false;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      if (k < n) {
+        double v = (do_hs && row_ok && pos >= k) ? (double)fabsf(M[k]) : -1.0;
+        int key = pos, who = r;
+        group_argmax<G>(v, key, who);
+        const float piv = __shfl(M[k], who, G);
+        if (piv == 0.0f) zero_pivot = true;
+        const int was = pos;
+        if (was == k) pos = key;  // exchange logical rows k and key
+        if (r == who) {
+          pos = k;
+#pragma unroll
+          for (int j = k; j < G; ++j) S.row[g][j] = M[j];
+        }
+        wave_lds_sync();
+        if (do_hs && row_ok && pos > k) {
+          const float l = M[k] / piv;
+          M[k] = l;
+#pragma unroll
+          for (int j = k + 1; j < G; ++j) {
+            if (j < n) {
+              const float prod = l * S.row[g][j];
+              M[j] = M[j] - prod;
+            }
+          }
+        }
+        wave_lds_sync();
+      }
+    }
+    if (row_ok) {
+#pragma unroll
+      for (int j = 0; j < G; ++j)
+        if (j < n && !isfinite(M[j])) bad = true;
+    }
+    // Forward substitution L z = P e_c for all columns c at once: the lane at
+    // logical row i holds z_i for every c; its right-hand side is e_r.
+    float z[G];
+#pragma unroll
+    for (int c = 0; c < G; ++c) z[c] = (c == r) ? 1.0f : 0.0f;
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      if (j < n) {
+        if (pos == j && row_ok) {
+#pragma unroll
+          for (int c = 0; c < G; ++c) S.row[g][c] = z[c];
+        }
+        wave_lds_sync();
+        if (do_hs && row_ok && pos > j) {
+          const float L = M[j];
+#pragma unroll
+          for (int c = 0; c < G; ++c) {
+            if (c < n) {
+              const float prod = L * S.row[g][c];
+              z[c] = z[c] - prod;
+            }
+          }
+        }
+        wave_lds_sync();
+      }
+    }
+    // Back substitution U x = z, logical rows from n-1 down: x_j = t / U_jj,
+    // and every earlier row subtracts U_ij x_j as x_j becomes known.
+#pragma unroll
+    for (int j = G - 1; j >= 0; --j) {
+      if (j < n) {
+        if (pos == j && row_ok) {
+          const float u = M[j];
+#pragma unroll
+          for (int c = 0; c < G; ++c) {
+            if (c < n) z[c] = z[c] / u;
+            S.row[g][c] = z[c];
+          }
+        }
+        wave_lds_sync();
+        if (do_hs && row_ok && pos < j) {
+          const float U = M[j];
+#pragma unroll
+          for (int c = 0; c < G; ++c) {
+            if (c < n) {
+              const float prod = U * S.row[g][c];
+              z[c] = z[c] - prod;
+            }
+          }
+        }
+        wave_lds_sync();
+      }
+    }
+    if (row_ok) {
+#pragma unroll
+      for (int c = 0; c < G; ++c)
+        if (c < n && !isfinite(z[c])) bad = true;
+    }
+    const bool skip = group_bits<G>(__ballot(bad || zero_pivot), g) != 0;
+    run = do_hs && !skip;
+
+    // H6, H7: this lane holds row `pos` of Y.
+    //   g_pos = sum_m Y[pos][m] F_m(x),  P[pos][j] = sum_m Y[pos][m] J[m][j],
+    // m ascending from the first term; exactly-zero terms are omitted.
+    iv P[G];
+    iv gv{0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < G; ++j) P[j] = iv{0.0, 0.0};
+    if (run && row_ok) {
+      uint32_t have = 0;
+      bool hg = false;
+      for (int m = 0; m < n; ++m) {
+        float ym = 0.0f;
+#pragma unroll
+        for (int c = 0; c < G; ++c)
+          if (c == m) ym = z[c];
+        const double y = (double)ym;
+        if (y != 0.0) {
+          const iv fm = S.Fc[g][m];
+          if (!is_zero(fm)) {
+            const iv t = pmul(y, fm);
+            gv = hg ? iadd(gv, t) : t;
+            hg = true;
+          }
+          const uint32_t nz = T.jnz[m];
+#pragma unroll
+          for (int j = 0; j < G; ++j) {
+            if (j < n && ((nz >> j) & 1u)) {
+              const iv t = pmul(y, S.J[g][m][j]);
+              P[j] = ((have >> j) & 1u) ? iadd(P[j], t) : t;
+              have |= 1u << j;
+            }
+          }
+        }
+      }
+    }
+    // S_U = sum_{j > pos} P[pos][j] (X_j - x_j), j ascending
+    iv SU{0.0, 0.0};
+    bool hasU = false;
+    if (run && row_ok) {
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        if (j < n && j > pos) {
+          const iv t = imul(P[j], S.D[g][j]);
+          SU = hasU ? iadd(SU, t) : t;
+          hasU = true;
+        }
+      }
+    }
+    // P rows replace J in LDS (row = logical position) for the sweep
+    wave_lds_sync();
+    if (run && row_ok) {
+#pragma unroll
+      for (int j = 0; j < G; ++j)
+        if (j < n) S.J[g][pos][j] = P[j];
+    }
+    wave_lds_sync();
+
+    // H9: Gauss-Seidel sweep (eq 21-22).  The bracket
+    //   g_i + sum_{j<i} P_ij (X'_j - x_j) + sum_{j>i} P_ij (X_j - x_j)
+    // is formed as (g_i + S_L) + S_U, each sum on its own, j ascending.
+    iv SL{0.0, 0.0};
+    bool hasL = false;
+    bool my_unique = true, my_empty = false;
+    for (int i = 0; i < n; ++i) {
+      if (run && row_ok && pos == i) {
+        iv N = gv;
+        if (hasL) N = iadd(N, SL);
+        if (hasU) N = iadd(N, SU);
+        const double xc = S.Xc[g][i].lo;
+        iv xn;
+        bool inside = false;
+        const bool ok = gs_component(N, S.J[g][i][i], xc, S.X[g][i], xn, inside);
+        my_empty = !ok;
+        my_unique = ok && inside;
+        if (!ok) xn = S.X[g][i];
+        S.Xn[g][i] = xn;
+        S.D[g][i] = isub(xn, point_iv(xc));
+      }
+      wave_lds_sync();
+      if (run && row_ok && pos > i) {
+        const iv t = imul(S.J[g][pos][i], S.D[g][i]);
+        SL = hasL ? iadd(SL, t) : t;
+        hasL = true;
+      }
+    }
+    hs_empty = run && group_bits<G>(__ballot(my_empty), g) != 0;
+    hs_unique = run && group_bits<G>(__ballot(row_ok && !my_unique), g) == 0;
+  }
+  // boxes without a contraction keep X as X'
+  if (active && !run && row_ok) S.Xn[g][r] = S.X[g][r];
+  wave_lds_sync();
+
+  // ---- decisions (S3-S7), uniform per group
+  const bool alive = active && !hs_empty;
+  const bool prv = proven || (alive && run && hs_unique);
+  double wn = (alive && row_ok) ? iwidth(S.Xn[g][r]) : -1.0;
+  int kk = r, whok = r;
+  group_argmax<G>(wn, kk, whok);
+
+  int n_push = 0;
+  bool emit = false;
+  int tag = 0;
+  int kind = 0;  // 0 none, 1 same box again, 2 widest split, 3 split all
+  uint32_t child_meta = 0;
+  double mid_kk = 0.0;
+  uint32_t split_mask = 0;
+  if (alive) {
+    if (wn <= a.tol) {
+      emit = true;
+      tag = prv ? 1 : 0;
+    } else if (prv) {
+      if (wn < w && rc + 1 < a.max_rc) {
+        kind = 1;
+        n_push = 1;
+        child_meta = 1u | ((uint32_t)(rc + 1) << 8);
+      } else {
+        emit = true;
+        tag = 1;
+      }
+    } else if (wn <= rmul(a.ratio, w) && rc + 1 < a.max_rc) {
+      kind = 1;
+      n_push = 1;
+      child_meta = (uint32_t)(rc + 1) << 8;
+    } else if (a.split_mode == 0) {
+      const iv xk = S.Xn[g][kk];
+      mid_kk = imid(xk);
+      if (!(mid_kk > xk.lo && mid_kk < -xk.nhi)) {
+        emit = true;
+        tag = 0;
+      } else {
+        kind = 2;
+        n_push = 2;
+      }
+    }
+  }
+  if (a.split_mode != 0) {
+    bool can = false;
+    if (alive && row_ok) {
+      const iv xr = S.Xn[g][r];
+      const double m = imid(xr);
+      can = m > xr.lo && m < -xr.nhi;
+    }
+    split_mask = (uint32_t)group_bits<G>(__ballot(can), g);
+    if (alive && !emit && kind == 0) {
+      if (split_mask == 0) {
+        emit = true;
+        tag = 0;
+      } else {
+        kind = 3;
+        n_push = 1 << __popc(split_mask);
+      }
+    }
+  }
+
+  // ---- counters, once per group
+  const bool leader = (r == 0) && valid;
+  sc.s[kProcessed] += __popcll(__ballot(leader));
+  sc.s[kExclEval] += __popcll(__ballot(leader && excluded));
+  sc.s[kExclHs] += __popcll(__ballot(leader && hs_empty));
+  sc.s[kHsSkipped] += __popcll(__ballot(leader && active && !run));
+  sc.s[kRecontract] += __popcll(__ballot(leader && kind == 1));
+  sc.s[kBisected] += __popcll(__ballot(leader && (kind == 2 || kind == 3)));
+  sc.s[kEmitU] += __popcll(__ballot(leader && emit && tag == 1));
+  sc.s[kEmitUnd] += __popcll(__ballot(leader && emit && tag == 0));
+
+  // ---- compaction: one atomic per wave for the pushes, one for the emits
+  const unsigned my_push = (r == 0) ? (unsigned)n_push : 0u;
+  const unsigned my_emit = (r == 0 && emit) ? 1u : 0u;
+  const unsigned incl_p = wave_inclusive_sum(my_push);
+  const unsigned incl_e = wave_inclusive_sum(my_emit);
+  const unsigned tot_p = __shfl(incl_p, 63, 64);
+  const unsigned tot_e = __shfl(incl_e, 63, 64);
+  unsigned long long pbase = 0, ebase = 0;
+  if (lane == 0) {
+    if (tot_p) pbase = atomicAdd(next_count, (unsigned long long)tot_p);
+    if (tot_e) ebase = atomicAdd(&a.ctrl->out_count, (unsigned long long)tot_e);
+  }
+  pbase = __shfl(pbase, 0, 64);
+  ebase = __shfl(ebase, 0, 64);
+  const unsigned gp = __shfl(incl_p - my_push, g * G, 64);
+  const unsigned ge = __shfl(incl_e - my_emit, g * G, 64);
+
+  const int nxt = cur ^ 1;
+  if (emit) {
+    const unsigned long long o = ebase + ge;
+    if (o < (unsigned long long)a.out_cap) {
+      if (row_ok) {
+        const iv x = S.Xn[g][r];
+        double* dst = a.out_box + ((size_t)o * G + r) * 2;
+        dst[0] = x.lo;
+        dst[1] = x.nhi;
+      }
+      if (r == 0) a.out_tag[o] = (uint32_t)tag;
+    }
+  }
+  if (n_push) {
+    const unsigned long long o = pbase + gp;
+    const iv x = row_ok ? S.Xn[g][r] : iv{0.0, 0.0};
+    if (kind == 1) {
+      if (o < (unsigned long long)a.front_cap) {
+        if (row_ok) {
+          double* dst = a.front[nxt] + ((size_t)o * G + r) * 2;
+          dst[0] = x.lo;
+          dst[1] = x.nhi;
+        }
+        if (r == 0) a.meta[nxt][o] = child_meta;
+      }
+    } else if (kind == 2) {
+      for (int c = 0; c < 2; ++c) {
+        if (o + c < (unsigned long long)a.front_cap) {
+          if (row_ok) {
+            iv y = x;
+            if (r == kk) y = c ? iv{mid_kk, x.nhi} : iv{x.lo, -mid_kk};
+            double* dst = a.front[nxt] + ((size_t)(o + c) * G + r) * 2;
+            dst[0] = y.lo;
+            dst[1] = y.nhi;
+          }
+          if (r == 0) a.meta[nxt][o + c] = 0u;
+        }
+      }
+    } else {
+      const bool mine = (split_mask >> r) & 1u;
+      const int q = __popc(split_mask & ((1u << r) - 1u));
+      const double m = row_ok ? imid(x) : 0.0;
+      for (int c = 0; c < n_push; ++c) {
+        if (o + c < (unsigned long long)a.front_cap) {
+          if (row_ok) {
+            iv y = x;
+            if (mine) y = ((c >> q) & 1) ? iv{m, x.nhi} : iv{x.lo, -m};
+            double* dst = a.front[nxt] + ((size_t)(o + c) * G + r) * 2;
+            dst[0] = y.lo;
+            dst[1] = y.nhi;
+          }
+          if (r == 0) a.meta[nxt][o + c] = 0u;
+        }
+      }
+    }
+  }
+  wave_lds_sync();
+}
+
+// ---------------------------------------------------------------------------
+// Grid barrier between levels.  Every wait is bounded: after timeout_ticks of
+// the 100 MHz device clock the barrier records IBB_ERR_TIMEOUT and returns, and
+// every later wait returns as soon as it sees a non-zero status.
+// ---------------------------------------------------------------------------
+__device__ void grid_barrier(const SolveArgs& a, unsigned long long& target) {
+  __threadfence();
+  __syncthreads();
+  target += (unsigned long long)a.nblocks;
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(&a.ctrl->bar, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long t0 = wall_clock64();
+    while (__hip_atomic_load(&a.ctrl->bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (__hip_atomic_load(&a.ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      if ((long long)(wall_clock64() - t0) > a.timeout_ticks) {
+        atomicCAS(&a.ctrl->status, 0, -8);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  __threadfence();
+}
+
+template <int G>
+__global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
+  set_fp64_round_down();
+  extern __shared__ __align__(16) char smem[];
+  const SysDesc* d = reinterpret_cast<const SysDesc*>(a.blob);
+  const LTable T = stage_table(a.blob, smem);
+  Scratch<G>* S =
+      reinterpret_cast<Scratch<G>*>(smem + align16(table_lds_bytes(d->n, d->T, d->TD))) + (threadIdx.x / 64);
+  __syncthreads();
+
+  constexpr int W = 64 / G;
+  StepCounters sc;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) sc.s[i] = 0;
+  unsigned long long processed = 0, target = 0;
+  const int lane = __lane_id();
+  Ctrl* c = a.ctrl;
+  for (int level = 0;; ++level) {
+    const unsigned long long cnt =
+        __hip_atomic_load(&c->count[level % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int st = __hip_atomic_load(&c->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (st != 0 || cnt == 0) break;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (level < a.level_cap) a.level_sizes[level] = (long long)cnt;
+      c->levels = (unsigned long long)(level + 1);
+      if (cnt > c->max_frontier) c->max_frontier = cnt;
+    }
+    // the budget is on tree nodes: it fails exactly when the tree has more
+    // than max_boxes nodes, whatever the frontier capacity
+    if (processed + cnt > (unsigned long long)a.max_boxes) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(&c->status, 0, -2);
+      break;
+    }
+    if (cnt > (unsigned long long)a.front_cap) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(&c->status, 0, -4);
+      break;
+    }
+    processed += cnt;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      __hip_atomic_store(&c->claim[(level + 1) % 3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&c->count[(level + 2) % 3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const int cur = level & 1;
+    unsigned long long* next_count = &c->count[(level + 1) % 3];
+    for (;;) {
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(&c->claim[level % 3], (unsigned long long)W);
+      base = __shfl(base, 0, 64);
+      if (base >= cnt) break;
+      step_tile<G>(a, T, *S, (long long)base, (long long)cnt, cur, next_count, sc);
+    }
+    grid_barrier(a, target);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (sc.s[i]) atomicAdd(&c->stats[i], sc.s[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Output: canonical (-0 -> +0) boxes sorted lexicographically by
+// (lo_0..lo_{n-1}, hi_0..hi_{n-1}, tag).  Each element finds its rank by
+// comparing with all others (ties broken by the original index).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int cmp_boxes(const double* A, uint32_t ta, const double* B, uint32_t tb, int n) {
+  for (int k = 0; k < n; ++k) {
+    const double a = A[2 * k], b = B[2 * k];
+    if (a < b) return -1;
+    if (a > b) return 1;
+  }
+  for (int k = 0; k < n; ++k) {  // stored as -hi
+    const double a = A[2 * k + 1], b = B[2 * k + 1];
+    if (a > b) return -1;
+    if (a < b) return 1;
+  }
+  return (ta < tb) ? -1 : (ta > tb ? 1 : 0);
+}
+
+__device__ __forceinline__ double canon(double x) { return x == 0.0 ? 0.0 : x; }
+
+__global__ void sort_kernel(const double* box, const uint32_t* tag, const Ctrl* c, int n, int G,
+                            long long out_cap, double* out_lo, double* out_hi, uint8_t* out_tag) {
+  const unsigned long long total = c->out_count;
+  if (c->status != 0 || total > (unsigned long long)out_cap) return;
+  const long long m = (long long)total;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double* A = box + (size_t)i * G * 2;
+  const uint32_t ta = tag[i];
+  long long rank = 0;
+  for (long long j = 0; j < m; ++j) {
+    const int s = cmp_boxes(box + (size_t)j * G * 2, tag[j], A, ta, n);
+    if (s < 0 || (s == 0 && j < i)) ++rank;
+  }
+  for (int k = 0; k < n; ++k) {
+    out_lo[(size_t)rank * n + k] = canon(A[2 * k]);
+    out_hi[(size_t)rank * n + k] = canon(-A[2 * k + 1]);
+  }
+  out_tag[rank] = (uint8_t)ta;
+}
+
+// d_info: status, box count, the eight tree counters, levels, widest level.
+__global__ void finalize_kernel(const Ctrl* c, long long out_cap, long long* info) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int st = c->status;
+  if (st == 0 && c->out_count > (unsigned long long)out_cap) st = -3;
+  info[0] = st;
+  info[1] = (long long)c->out_count;
+  for (int i = 0; i < 8; ++i) info[2 + i] = (long long)c->stats[i];
+  info[10] = (long long)c->levels;
+  info[11] = (long long)c->max_frontier;
+}
+
+// Initial state of a solve: control block, the root box at level 0.
+__global__ void init_kernel(Ctrl* c, double* front0, uint32_t* meta0, const double* lo, const double* hi,
+                            int n, int G) {
+  const int t = threadIdx.x;
+  if (t < (int)(sizeof(Ctrl) / 8)) reinterpret_cast<unsigned long long*>(c)[t] = 0ull;
+  if (t < G) {
+    front0[2 * t] = t < n ? lo[t] : 0.0;
+    front0[2 * t + 1] = t < n ? -hi[t] : 0.0;
+  }
+  if (t == 0) meta0[0] = 0u;
+  __syncthreads();
+  if (t == 0) c->count[0] = 1ull;
+}
+
+// Diagnostics: the device rounding primitives on operand arrays.
+__global__ void selftest_kernel(int op, long long count, const double* x, const double* y, double* out) {
+  set_fp64_round_down();
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const double a = x[i], b = y[i];
+  double r = 0.0;
+  switch (op) {
+    case 0: r = radd(a, b); break;
+    case 1: r = -radd(-a, -b); break;
+    case 2: r = rsub(a, b); break;
+    case 3: r = -rsub(-a, -b); break;
+    case 4: r = rmul(a, b); break;
+    case 5: r = -rmul_neg(a, b); break;
+    case 6: r = rd_div(a, b); break;
+    case 7: r = ru_div(a, b); break;
+    case 8: r = (double)narrow_rn(a); break;
+    case 9: r = imid(make_iv(a, b)); break;
+    case 10: {
+      const float fa = (float)a, fb = (float)b;
+      const float p = fa * fb;
+      r = (double)p;
+      break;
+    }
+    case 11: {
+      const float fa = (float)a, fb = (float)b;
+      const float q = fa / fb;
+      r = (double)q;
+      break;
+    }
+    default: r = 0.0;
+  }
+  out[i] = r;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch helpers (called by the runtime in api.cpp).
+// ---------------------------------------------------------------------------
+size_t scratch_bytes(int G) {
+  switch (G) {
+    case 2: return sizeof(Scratch<2>);
+    case 4: return sizeof(Scratch<4>);
+    case 8: return sizeof(Scratch<8>);
+    default: return sizeof(Scratch<16>);
+  }
+}
+
+const void* solve_kernel_ptr(int G) {
+  switch (G) {
+    case 2: return reinterpret_cast<const void*>(&solve_kernel<2>);
+    case 4: return reinterpret_cast<const void*>(&solve_kernel<4>);
+    case 8: return reinterpret_cast<const void*>(&solve_kernel<8>);
+    default: return reinterpret_cast<const void*>(&solve_kernel<16>);
+  }
+}
+
+hipError_t launch_init(hipStream_t s, Ctrl* c, double* front0, uint32_t* meta0, const double* lo,
+                       const double* hi, int n, int G) {
+  hipLaunchKernelGGL(init_kernel, dim3(1), dim3(64), 0, s, c, front0, meta0, lo, hi, n, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort(hipStream_t s, const double* box, const uint32_t* tag, const Ctrl* c, int n, int G,
+                       long long out_cap, double* out_lo, double* out_hi, uint8_t* out_tag,
+                       long long grid_elems) {
+  const int blocks = (int)((grid_elems + 255) / 256);
+  if (blocks > 0)
+    hipLaunchKernelGGL(sort_kernel, dim3(blocks), dim3(256), 0, s, box, tag, c, n, G, out_cap, out_lo,
+                       out_hi, out_tag);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(hipStream_t s, const Ctrl* c, long long out_cap, long long* info) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, s, c, out_cap, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_selftest(hipStream_t s, int op, long long count, const double* x, const double* y,
+                           double* out) {
+  const int blocks = (int)((count + 255) / 256);
+  if (blocks > 0) hipLaunchKernelGGL(selftest_kernel, dim3(blocks), dim3(256), 0, s, op, count, x, y, out);
+  return hipGetLastError();
+}
+
+}  // namespace ibb

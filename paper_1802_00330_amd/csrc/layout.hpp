@@ -1,0 +1,74 @@
+// layout.hpp -- data layouts shared by the host runtime and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ibb {
+
+constexpr int kMaxN = 16;
+constexpr int kBlock = 256;  // threads per workgroup (4 waves of 64)
+constexpr int kInfoLen = 16;
+
+// Compiled system, one contiguous blob of 8-byte words in device memory:
+//   [0, 16)           SysDesc
+//   eq_off            int32 [n+1]        terms of equation i: eq_off[i] .. eq_off[i+1]-1
+//   der_off           int32 [n*n+1]      derivative terms of (i,k): der_off[i*n+k] ..
+//   coef              double [T]         term coefficients
+//   fac               uint64 [T]         factors, byte q = (pow << 4) | var, var ascending, 0 ends
+//   dcoef             double [TD]        coefficient c of the parent term
+//   dmult             uint32 [TD]        exponent e_k of the differentiated variable
+//   dfac              uint64 [TD]        factors of the lowered monomial (may be 0 = constant)
+// Offsets are in 8-byte words from the start of the blob.
+struct SysDesc {
+  int32_t n, G, T, TD;
+  int32_t eq_off_w, der_off_w, coef_w, fac_w;
+  int32_t dcoef_w, dmult_w, dfac_w, total_w;
+  uint32_t jnz[kMaxN];  // bit k of jnz[i]: d f_i / d x_k has at least one term
+  int32_t pad[4];
+};
+static_assert(sizeof(SysDesc) == 128, "SysDesc size");
+
+// Control block of one solve (device memory, zero-initialised by the host
+// except count[0] = 1).
+struct Ctrl {
+  unsigned long long count[3];   // frontier size of level L in count[L % 3]
+  unsigned long long claim[3];   // next unclaimed box of level L in claim[L % 3]
+  unsigned long long out_count;  // emitted boxes
+  unsigned long long bar;        // grid-barrier arrivals (monotone)
+  unsigned long long stats[8];   // processed, excluded_eval, excluded_hs, hs_skipped,
+                                 // recontracted, bisected, emitted_unique, emitted_undecided
+  unsigned long long levels;
+  unsigned long long max_frontier;
+  int32_t status;
+  int32_t pad[7];
+};
+
+struct SolveArgs {
+  const uint64_t* blob;
+  double* front[2];  // boxes as (lo, -hi) pairs, [cap][G][2]
+  uint32_t* meta[2]; // bit 0 proven, bits 8..15 consecutive re-contractions
+  long long front_cap;
+  double* out_box;   // [out_cap][G][2]
+  uint32_t* out_tag;
+  long long out_cap;
+  Ctrl* ctrl;
+  long long* level_sizes;
+  long long level_cap;
+  double tol, ratio, hs_max_width;
+  long long max_boxes;
+  int split_mode, max_rc;
+  int nblocks;
+  int pad;
+  long long timeout_ticks;  // device wall-clock ticks (100 MHz) a barrier may wait
+};
+
+// LDS bytes of the staged system table (kernels.hip, stage_table).
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+__host__ __device__ inline size_t table_lds_bytes(int n, int T, int TD) {
+  return align16(sizeof(int) * (n + 1)) + align16(sizeof(int) * (n * n + 1)) +
+         align16(sizeof(uint32_t) * kMaxN) + align16(sizeof(double) * T) + align16(sizeof(uint64_t) * T) +
+         align16(16 * (size_t)TD) + align16(sizeof(uint64_t) * TD);
+}
+
+}  // namespace ibb

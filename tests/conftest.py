@@ -18,3 +18,11 @@ def oracle_lib():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def gpu_ctx():
+    import paper_1802_00330_amd as P
+    ctx = P.Context(0)
+    yield ctx
+    ctx.close()

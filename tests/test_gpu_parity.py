@@ -1,0 +1,126 @@
+"""GPU search vs the CPU oracle on the same seeded systems: sorted box lists
+bit-exact, identical tree counters.  Sizes are chosen so the oracle finishes in
+seconds while the device levels still span many tiles with ragged tails."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.parity import assert_same
+
+pytestmark = pytest.mark.gpu
+
+
+def _both(ctx, oracle_lib, s, **kw):
+    import paper_1802_00330_amd as P
+    print(f"[parity] {s.name} n={s.n} T={s.n_terms} {kw}", flush=True)
+    ref = oracle_lib.solve(s, **kw)
+    gpu = P.solve(ctx, s, **kw)
+    return gpu, ref
+
+
+def test_circle_line(gpu_ctx, oracle_lib):
+    gpu, ref = _both(gpu_ctx, oracle_lib, W.circle_line())
+    assert_same(gpu, ref, "circle_line")
+    assert gpu.tag.tolist() == [1, 1]
+
+
+def test_circle_line_split_all(gpu_ctx, oracle_lib):
+    gpu, ref = _both(gpu_ctx, oracle_lib, W.circle_line(), split_mode=1)
+    assert_same(gpu, ref, "circle_line ALL")
+
+
+def test_host_pointer_entry_point(gpu_ctx, oracle_lib):
+    import paper_1802_00330_amd as P
+    s = W.circle_line()
+    gpu = P.ibb_solve(gpu_ctx, s, P.make_params(s.tol))
+    assert_same(gpu, oracle_lib.solve(s), "ibb_solve")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_univariate(gpu_ctx, oracle_lib, seed):
+    rng = np.random.default_rng(seed)
+    roots = np.sort(rng.uniform(-1.9, 1.9, size=int(rng.integers(2, 7))))
+    c = np.poly(roots)[::-1]
+    s = W.univariate(c, -2.0, 2.0, tol=1e-10)
+    gpu, ref = _both(gpu_ctx, oracle_lib, s)
+    assert_same(gpu, ref, s.name)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+def test_product_systems(gpu_ctx, oracle_lib, n):
+    s = W.product_linear([4, n], n=n)
+    gpu, ref = _both(gpu_ctx, oracle_lib, s)
+    assert_same(gpu, ref, s.name)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_dense_small(gpu_ctx, oracle_lib, seed):
+    s = W.dense_planted(seed, n=4, n_terms=6, max_deg=2)
+    gpu, ref = _both(gpu_ctx, oracle_lib, s)
+    assert_same(gpu, ref, s.name)
+
+
+def test_dense_n5_cubic(gpu_ctx, oracle_lib):
+    s = W.dense_planted(0, n=5, n_terms=8, max_deg=3)
+    gpu, ref = _both(gpu_ctx, oracle_lib, s)
+    assert_same(gpu, ref, s.name)
+
+
+@pytest.mark.parametrize("n", [4, 6, 8])
+def test_banded(gpu_ctx, oracle_lib, n):
+    s = W.banded(0, n=n, tol=1e-8)
+    gpu, ref = _both(gpu_ctx, oracle_lib, s)
+    assert_same(gpu, ref, s.name)
+
+
+@pytest.mark.parametrize("w", [0.05, 0.2])
+def test_dense_n6_subbox(gpu_ctx, oracle_lib, w):
+    s = W.dense_planted(0)
+    r = s.roots[0]
+    gpu, ref = _both(gpu_ctx, oracle_lib, s, lo=r - 0.7 * w, hi=r + 1.3 * w)
+    assert_same(gpu, ref, f"dense n=6 sub-box {w}")
+
+
+@pytest.mark.parametrize("k", [9, 11])
+def test_batch_members(gpu_ctx, oracle_lib, k):
+    s = W.batch_planted(0, indices=[k])[0]
+    gpu, ref = _both(gpu_ctx, oracle_lib, s)
+    assert_same(gpu, ref, s.name)
+
+
+def test_budget_error(gpu_ctx, oracle_lib):
+    s = W.circle_line()
+    full = oracle_lib.solve(s)
+    n = full.stats["processed"]
+    import paper_1802_00330_amd as P
+    assert P.solve(gpu_ctx, s, max_boxes=n).status == 0
+    assert P.solve(gpu_ctx, s, max_boxes=n - 1).status == P.ERR_BUDGET
+
+
+def test_rootless_box_and_point_box(gpu_ctx, oracle_lib):
+    s = W.circle_line()
+    gpu, ref = _both(gpu_ctx, oracle_lib, s, lo=[1.0, -2.0], hi=[2.0, -1.0])
+    assert_same(gpu, ref, "rootless")
+    assert len(gpu.tag) == 0
+    x = 0.5 ** 0.5
+    gpu, ref = _both(gpu_ctx, oracle_lib, s, lo=[x, x], hi=[x, x])
+    assert_same(gpu, ref, "point box")
+
+
+def test_invalid_arguments(gpu_ctx):
+    import paper_1802_00330_amd as P
+    s = W.circle_line()
+    assert P.solve(gpu_ctx, s, tol=0.0).status == P.ERR_INVALID_ARG
+    bad = W.circle_line()
+    bad.coef[0] = float("nan")
+    assert P.solve(gpu_ctx, bad).status == P.ERR_INVALID_ARG
+
+
+def test_frontier_overflow_retry(gpu_ctx, oracle_lib):
+    """A tiny frontier forces QUEUE_OVERFLOW; the binding grows it and the
+    result is unchanged."""
+    import paper_1802_00330_amd as P
+    s = W.product_linear([4, 4], n=4)
+    ref = oracle_lib.solve(s)
+    gpu = P.solve(gpu_ctx, s, frontier_cap=4, out_cap=2)
+    assert_same(gpu, ref, "overflow retry")
