@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark: boxes/s and solves/s of the interval branch-and-bound search on one
+MI355X, with the roofline fraction of the search kernel and the CPU oracle timed
+beside it.
+
+One step = one complete solve (every tree level, output sort) of the dense
+planted system: n = 6 equations in 6 variables, 20 monomials of total degree
+1..3 per equation plus a constant term, coefficients U[-1,1], a planted root
+r ~ U[-1,1]^6, initial box [-2,2]^6, width tolerance 1e-8, FP64 intervals with
+an FP32 preconditioner (seed 0).  Inputs are resident in device memory before
+the timed region except the few-KB system description, which each solve
+compiles and copies in.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "boxes/sec and solves/sec (p50/p99 latency), batched vs plain, bit-exact boxes"
+FP64_PEAK = 78.6e12  # MI355X FP64 vector, FLOP/s
+HBM_PEAK = 8.0e12    # bytes/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def flop_model(s):
+    """Algorithmic work per tree node (1 flop = one directed-rounded FP64 op;
+    an interval op counts one flop per bound).  Returns (exclusion-only box,
+    contracted box FP64, contracted box FP32)."""
+    import numpy as np
+    n = s.n
+    deg = s.expo.sum(axis=1).astype(np.int64)
+    f_eval = int(np.sum(2 * deg + 2))
+    f_jac = 0
+    nnz = 0
+    for i in range(n):
+        a, b = int(s.term_off[i]), int(s.term_off[i + 1])
+        for k in range(n):
+            dk = [int(deg[t]) for t in range(a, b) if s.expo[t, k] > 0]
+            f_jac += sum(2 * d for d in dk)
+            nnz += 1 if dk else 0
+    f_hs = 2 * f_eval + f_jac + 2 * n * n + 4 * n * nnz + 8 * n * n + 4 * n
+    f32 = (8 * n ** 3) // 3
+    return f_eval, f_hs, f32
+
+
+def cpu_baseline(s, sample_nodes):
+    import oracle
+    t = time.perf_counter()
+    r = oracle.solve(s, max_boxes=sample_nodes)
+    dt = time.perf_counter() - t
+    done = r.stats["processed"] if r.status == 0 else sample_nodes
+    return {"value": done / dt, "unit": "boxes/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} tree nodes (last-in-first-out order) of the same solve, one thread, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-sample", type=int, default=300_000, help="tree nodes the oracle times (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: the search has no multi-GPU path in this build "
+              "(see DESIGN.md for how it would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1802_00330_amd as P
+    import workloads as W
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    dev = torch.device("cuda:0")
+    ctx = P.Context(0)
+    s = W.dense_planted(args.seed)
+    params = P.make_params(s.tol)
+    stream = torch.cuda.current_stream(dev)
+
+    # device buffers sized on a first (warm-up) solve
+    fcap, ocap = 1 << 20, 1 << 10
+    while True:
+        ws = torch.empty(P.ibb_workspace_size(s.n, fcap, ocap), dtype=torch.uint8, device=dev)
+        olo = torch.empty(ocap * s.n, dtype=torch.float64, device=dev)
+        ohi = torch.empty_like(olo)
+        otag = torch.empty(ocap, dtype=torch.uint8, device=dev)
+        info = torch.zeros(16, dtype=torch.int64, device=dev)
+        st = P.ibb_solve_async(ctx, s, params, ws, fcap, ocap, olo, ohi, otag, info, stream=stream)
+        assert st == P.OK, P.ibb_strerror(st)
+        stream.synchronize()
+        inf = info.cpu().numpy()
+        if inf[0] == P.ERR_QUEUE_OVERFLOW:
+            fcap *= 4
+            continue
+        if inf[0] == P.ERR_OUTPUT_CAPACITY:
+            ocap = int(inf[1])
+            continue
+        assert inf[0] == P.OK, P.ibb_strerror(int(inf[0]))
+        break
+    log(f"[bench] warm solve: {int(inf[2])} nodes, {int(inf[1])} boxes, {int(inf[10])} levels, "
+        f"widest level {int(inf[11])}, frontier cap {fcap}")
+    for _ in range(max(0, args.warmup - 1)):
+        P.ibb_solve_async(ctx, s, params, ws, fcap, ocap, olo, ohi, otag, info, stream=stream)
+    torch.cuda.synchronize()
+
+    lat, kms = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        a = time.perf_counter()
+        P.ibb_solve_async(ctx, s, params, ws, fcap, ocap, olo, ohi, otag, info, stream=stream)
+        stream.synchronize()
+        lat.append(time.perf_counter() - a)
+        kms.append(P.ibb_last_kernel_ms(ctx))
+        log(f"[bench] step {k}: {lat[-1] * 1e3:.2f} ms (search kernel {kms[-1]:.2f} ms)")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    inf = info.cpu().numpy()
+    assert inf[0] == P.OK
+    nodes = int(inf[2])
+    elapsed = t1 - t0
+    value = nodes * args.steps / elapsed
+
+    # bit-exactness against the stored oracle result of the same solve
+    exact = None
+    gold = os.path.join(ROOT, "tests", "golden", f"expected_dense6_s{args.seed}.json")
+    if os.path.exists(gold):
+        g = json.load(open(gold))
+        m = int(inf[1])
+        lo = olo[: m * s.n].view(m, s.n).cpu().numpy()
+        hi = ohi[: m * s.n].view(m, s.n).cpu().numpy()
+        tag = otag[:m].cpu().numpy()
+        exp_lo = np.array([[float.fromhex(v) for v in row] for row in g["lo"]]).reshape(-1, s.n)
+        exp_hi = np.array([[float.fromhex(v) for v in row] for row in g["hi"]]).reshape(-1, s.n)
+        stats = dict(zip(P.STATS_FIELDS, (int(v) for v in inf[2:10])))
+        exact = bool(g["status"] == 0 and stats == g["stats"] and lo.shape == exp_lo.shape
+                     and np.array_equal(lo.view(np.uint64), exp_lo.view(np.uint64))
+                     and np.array_equal(hi.view(np.uint64), exp_hi.view(np.uint64))
+                     and tag.tolist() == g["tag"])
+
+    f_eval, f_hs, f32 = flop_model(s)
+    excl = int(inf[3])
+    contracted = nodes - excl
+    flops = excl * f_eval + contracted * f_hs + contracted * f32 / 2.0  # FP32 at twice the FP64 rate
+    kmean = float(np.mean(kms)) / 1e3
+    achieved = flops / kmean
+    G = 8
+    bytes_alg = nodes * (16 * G + 4) + (int(inf[7]) * 2 + int(inf[6])) * (16 * G + 4)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "boxes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "dense planted polynomial system, n=6, 20 monomials of degree 1..3 + constant "
+                               "per equation, box [-2,2]^6, tol 1e-8, one solve per step",
+                   "seed": args.seed, "tree_nodes": nodes, "output_boxes": int(inf[1]),
+                   "tree_levels": int(inf[10]), "widest_level": int(inf[11]), "split": "widest"},
+        "solves_per_s": args.steps / elapsed,
+        "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
+        "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
+        "kernel_ms_mean": kmean * 1e3,
+        "bit_exact_vs_oracle": exact,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK, "traffic": None,
+                     "algorithmic_bytes_per_launch": bytes_alg},
+    }
+    if args.cpu_sample > 0:
+        log(f"[bench] timing the oracle on {args.cpu_sample} nodes")
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_sample)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -145,6 +145,12 @@ int ibb_solve_async(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const
  * and the contraction is off (hs_max_width = 0). */
 int64_t ibb_last_level_sizes(ibb_ctx* ctx, int64_t* sizes, int64_t cap);
 
+/* Device time (ms) of the persistent search kernel of the most recent solve
+ * enqueued on this context (either entry point), measured with HIP events
+ * recorded on the solve's stream around the launch; waits for that event.
+ * Returns -1 if no solve was enqueued. */
+double ibb_last_kernel_ms(ibb_ctx* ctx);
+
 /* Diagnostics: apply one rounding primitive of the device arithmetic to n
  * operand pairs (host arrays) -- op 0..7 = rd/ru of + - * /, 8 = narrowing to
  * single precision (round to nearest, result widened), 9 = midpoint

@@ -30,7 +30,8 @@ STATS_FIELDS = ("processed", "excluded_eval", "excluded_hs", "hs_skipped", "reco
                 "bisected", "emitted_unique", "emitted_undecided")
 
 EXPORTS = ("ibb_ctx_create", "ibb_ctx_destroy", "ibb_strerror", "ibb_params_default", "ibb_solve",
-           "ibb_workspace_size", "ibb_solve_async", "ibb_last_level_sizes", "ibb_selftest_ops")
+           "ibb_workspace_size", "ibb_solve_async", "ibb_last_level_sizes", "ibb_last_kernel_ms",
+           "ibb_selftest_ops")
 
 
 class IbbSystem(C.Structure):
@@ -73,6 +74,7 @@ def load_library(path: str = LIB_PATH):
                                   p, p, p, p, p]
     L.ibb_last_level_sizes.restype, L.ibb_last_level_sizes.argtypes = i64, [p, p, i64]
     L.ibb_selftest_ops.restype, L.ibb_selftest_ops.argtypes = C.c_int, [p, i32, i64, p, p, p]
+    L.ibb_last_kernel_ms.restype, L.ibb_last_kernel_ms.argtypes = C.c_double, [p]
     _lib = L
     return L
 
@@ -169,6 +171,10 @@ def ibb_last_level_sizes(ctx: Context, cap: int = 1 << 16) -> np.ndarray:
     buf = np.zeros(cap, dtype=np.int64)
     m = load_library().ibb_last_level_sizes(ctx.handle, _ptr(buf), int(cap))
     return buf[:min(m, cap)].copy()
+
+
+def ibb_last_kernel_ms(ctx: Context) -> float:
+    return float(load_library().ibb_last_kernel_ms(ctx.handle))
 
 
 def ibb_workspace_size(n: int, frontier_cap: int, out_cap: int) -> int:

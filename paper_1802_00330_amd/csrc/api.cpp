@@ -200,6 +200,7 @@ struct ibb_ctx {
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, staged = nullptr;
   bool staged_pending = false;
+  bool timed_pending = false;  // ev0/ev1 bracket the last persistent launch
   void* ws = nullptr;  // workspace of the host-pointer entry points
   size_t ws_bytes = 0;
   double* sorted = nullptr;  // sorted outputs of ibb_solve (lo, hi, tag)
@@ -246,7 +247,7 @@ int ensure_pinned(ibb_ctx* ctx, size_t need) {
 int enqueue_solve(ibb_ctx* ctx, const Compiled& c, const double* lo, const double* hi,
                   const ibb_params* p, char* ws, const WsLayout& L, long long frontier_cap,
                   long long out_cap, double* d_out_lo, double* d_out_hi, uint8_t* d_out_tag,
-                  long long* d_info, hipStream_t s, bool timed) {
+                  long long* d_info, hipStream_t s) {
   const int n = c.n, G = c.G;
   // stage the host inputs: blob, lo, hi
   const size_t blob_bytes = 8 * c.blob.size();
@@ -306,10 +307,11 @@ int enqueue_solve(ibb_ctx* ctx, const Compiled& c, const double* lo, const doubl
   const int blocks = per_cu * ctx->num_cu;
   a.nblocks = blocks;
   void* args[] = {&a};
-  if (timed) hipEventRecord(ctx->ev0, s);
+  hipEventRecord(ctx->ev0, s);
   if (hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(64 * waves), args, (unsigned)lds, s) != hipSuccess)
     return IBB_ERR_DEVICE;
-  if (timed) hipEventRecord(ctx->ev1, s);
+  hipEventRecord(ctx->ev1, s);
+  ctx->timed_pending = true;
   if (launch_sort(s, a.out_box, a.out_tag, ctrl, n, G, out_cap, d_out_lo, d_out_hi, d_out_tag, out_cap) !=
       hipSuccess)
     return IBB_ERR_DEVICE;
@@ -431,7 +433,7 @@ int ibb_solve_async(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const
   const WsLayout L = ws_layout(c.n, max_blob_words(c.n), frontier_cap, out_cap);
   return enqueue_solve(ctx, c, lo, hi, params, static_cast<char*>(d_ws), L, frontier_cap, out_cap, d_out_lo,
                        d_out_hi, d_out_tag, reinterpret_cast<long long*>(d_info),
-                       static_cast<hipStream_t>(stream), false);
+                       static_cast<hipStream_t>(stream));
 }
 
 int ibb_solve(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const double* hi,
@@ -462,7 +464,7 @@ int ibb_solve(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const doubl
     double* d_hi = d_lo + (size_t)ocap * n;
     uint8_t* d_tag = reinterpret_cast<uint8_t*>(d_hi + (size_t)ocap * n);
     st = enqueue_solve(ctx, c, lo, hi, params, static_cast<char*>(ctx->ws), L, fcap, ocap, d_lo, d_hi, d_tag,
-                       ctx->info, ctx->stream, true);
+                       ctx->info, ctx->stream);
     if (st) return st;
     if (hipMemcpyAsync(info, ctx->info, sizeof info, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess)
@@ -498,6 +500,14 @@ int ibb_solve(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const doubl
     return IBB_OK;
   }
   return IBB_ERR_NO_MEMORY;
+}
+
+double ibb_last_kernel_ms(ibb_ctx* ctx) {
+  if (!ctx || !ctx->timed_pending) return -1.0;
+  if (hipEventSynchronize(ctx->ev1) != hipSuccess) return -1.0;
+  float ms = 0.0f;
+  if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) != hipSuccess) return -1.0;
+  return (double)ms;
 }
 
 int64_t ibb_last_level_sizes(ibb_ctx* ctx, int64_t* sizes, int64_t cap) {
