@@ -59,6 +59,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built; run paper_1802_00330_amd/build.py (hipcc, gfx950)")
+    # PyTorch bundles its own HIP runtime and loads it under a name that does
+    # not match an already loaded system copy.  Importing torch first makes the
+    # library bind to torch's runtime, so one HIP runtime serves both.
+    import torch  # noqa: F401
     L = C.CDLL(path)
     p, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.ibb_ctx_create.restype, L.ibb_ctx_create.argtypes = C.c_int, [C.c_int, C.POINTER(C.c_void_p)]
@@ -211,6 +215,8 @@ def solve(ctx: Context, s, tol: Optional[float] = None, frontier_cap: int = 1 <<
     grows the frontier / output buffers and retries on capacity errors."""
     import torch
 
+    lo = kw.pop("lo", None)
+    hi = kw.pop("hi", None)
     params = make_params(s.tol if tol is None else tol, **kw)
     while True:
         nbytes = ibb_workspace_size(s.n, frontier_cap, out_cap)
@@ -219,7 +225,8 @@ def solve(ctx: Context, s, tol: Optional[float] = None, frontier_cap: int = 1 <<
         ohi = torch.empty_like(olo)
         otag = torch.empty(max(out_cap, 1), dtype=torch.uint8, device=device)
         info = torch.zeros(16, dtype=torch.int64, device=device)
-        st = ibb_solve_async(ctx, s, params, ws, frontier_cap, out_cap, olo, ohi, otag, info, stream=stream)
+        st = ibb_solve_async(ctx, s, params, ws, frontier_cap, out_cap, olo, ohi, otag, info, stream=stream,
+                             lo=lo, hi=hi)
         if st != OK:
             return Result(st, np.zeros((0, s.n)), np.zeros((0, s.n)), np.zeros(0, np.uint8), {})
         (stream or torch.cuda.current_stream()).synchronize()

@@ -127,15 +127,16 @@ __device__ __forceinline__ double quot12(double ma, double mb, bool up) {
   return q;
 }
 
-// R(t * 2^e) for t > 0 a directed rounding (in the same direction) of the
-// exact value, e in [-2200, 2200]; neg selects -R(-(t * 2^e)) instead.
-__device__ __forceinline__ double scale2(double t, int e, bool neg) {
+// t * 2^e for t > 0 (itself a directed rounding of the exact value in the
+// same direction), e in [-2200, 2200], rounded down (up = false) or up: the
+// first scaling stays in the normal range and is exact, the second rounds once.
+__device__ __forceinline__ double scale2(double t, int e, bool up) {
   int e1 = e < -1000 ? -1000 : (e > 1000 ? 1000 : e);
-  double s = rmul(t, pow2(e1));  // exact: stays in the normal range
+  double s = rmul(t, pow2(e1));
   int e2 = e - e1;
-  if (e2 == 0) return neg ? -s : s;
+  if (e2 == 0) return s;
   e2 = e2 < -1074 ? -1074 : (e2 > 1023 ? 1023 : e2);
-  return neg ? -rmul_neg(s, pow2(e2)) : rmul(s, pow2(e2));
+  return up ? -rmul_neg(s, pow2(e2)) : rmul(s, pow2(e2));
 }
 
 // Correctly rounded quotients of finite a and non-zero finite b.
@@ -147,7 +148,7 @@ __device__ __forceinline__ double rd_div(double a, double b) {
   bool neg = ((f64_to_bits(a) ^ f64_to_bits(b)) >> 63) != 0;
   int ea, eb;
   double ma = frexp12(a, ea), mb = frexp12(b, eb);
-  // positive quotient: round down; negative: -(round up of the magnitude)
+  // positive quotient: round the magnitude down; negative: round it up, negate
   double q = quot12(ma, mb, neg);
   double r = scale2(q, ea - eb, neg);
   return neg ? -r : r;

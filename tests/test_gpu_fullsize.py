@@ -1,0 +1,44 @@
+"""Full-size workloads on the device against the oracle's stored results
+(written by tests/golden/make_expected.py, which calls only the oracle):
+bit-identical sorted box lists and tree counters."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+CASES = {
+    "dense6_s0": lambda: W.dense_planted(0),
+    "dense6_s1": lambda: W.dense_planted(1),
+    "banded12_s0": lambda: W.banded(0),
+    "banded12_s1": lambda: W.banded(1),
+}
+
+
+def _load(name):
+    path = os.path.join(GOLD, f"expected_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored oracle result {path}")
+    return json.load(open(path))
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_full_size_matches_stored_oracle(gpu_ctx, name):
+    import paper_1802_00330_amd as P
+    g = _load(name)
+    s = CASES[name]()
+    print(f"[fullsize] {name}: {g['stats']['processed']} nodes", flush=True)
+    r = P.solve(gpu_ctx, s)
+    assert r.status == g["status"] == 0
+    assert r.stats == g["stats"]
+    lo = np.array([[float.fromhex(v) for v in row] for row in g["lo"]]).reshape(-1, s.n)
+    hi = np.array([[float.fromhex(v) for v in row] for row in g["hi"]]).reshape(-1, s.n)
+    assert np.array_equal(r.lo.view(np.uint64), lo.view(np.uint64))
+    assert np.array_equal(r.hi.view(np.uint64), hi.view(np.uint64))
+    assert r.tag.tolist() == g["tag"]
