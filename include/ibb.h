@@ -119,6 +119,23 @@ int ibb_solve(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const doubl
               const ibb_params* params, double* out_lo, double* out_hi, uint8_t* out_tag,
               int64_t cap, int64_t* n_out, ibb_stats* stats);
 
+/* Solve B independent systems in one pass over the device (systems bucketed
+ * by size, each bucket one persistent launch).  Per system b: systems[b],
+ * its box lo/hi[b*IBB_MAX_N .. b*IBB_MAX_N + n_b) (host, stride IBB_MAX_N),
+ * params[b].  Outputs (host): boxes of all systems back to back, system b's
+ * boxes being out_off[b] .. out_off[b+1]-1 (out_off has B+1 entries), each box
+ * stored with stride IBB_MAX_N in out_lo/out_hi ([cap*IBB_MAX_N]) and its tag in
+ * out_tag[cap], sorted per system as in ibb_solve; status[b] is the system's
+ * own status (IBB_OK, IBB_ERR_INVALID_ARG, IBB_ERR_BUDGET; a failed system
+ * returns no boxes) and stats[b] its counters (levels and max_frontier are 0)
+ * when stats is not NULL.  Each system's result equals ibb_solve on it alone.
+ * Returns IBB_OK, IBB_ERR_OUTPUT_CAPACITY (out_off filled: out_off[B] is the
+ * required capacity) or a device error. */
+int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const double* lo,
+                    const double* hi, const ibb_params* params, double* out_lo, double* out_hi,
+                    uint8_t* out_tag, int64_t cap, int64_t* out_off, int32_t* status,
+                    ibb_stats* stats);
+
 /* Device workspace (bytes) that ibb_solve_async needs for a system with n
  * variables, a frontier of `frontier_cap` boxes per tree level and `out_cap`
  * output boxes. */
@@ -150,6 +167,15 @@ int64_t ibb_last_level_sizes(ibb_ctx* ctx, int64_t* sizes, int64_t cap);
  * recorded on the solve's stream around the launch; waits for that event.
  * Returns -1 if no solve was enqueued. */
 double ibb_last_kernel_ms(ibb_ctx* ctx);
+
+/* Diagnostics: run the search step on the single box [lo, hi] (one tree
+ * level) and copy its intermediates to `dump` (host, >= 6n^2 + 8n + 4
+ * doubles): J(X) [n][n][2], F(mid X) [n][2], the single-precision mid J
+ * [n][n], the preconditioner Y [n][n], g [n][2], P [n][n][2] (rows by pivot
+ * position), the bracket N_i [n][2], the contracted box [n][2], and flags
+ * (skipped, empty, unique, ran).  Intervals as (lo, hi). */
+int ibb_debug_step(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const double* hi,
+                   const ibb_params* params, double* dump, int64_t dump_len);
 
 /* Diagnostics: apply one rounding primitive of the device arithmetic to n
  * operand pairs (host arrays) -- op 0..7 = rd/ru of + - * /, 8 = narrowing to

@@ -57,6 +57,8 @@ def lib():
         L.oracle_eval_J.restype, L.oracle_eval_J.argtypes = None, [C.c_int, p, p, p, p, p, p, p]
         L.oracle_fp32_inverse.restype, L.oracle_fp32_inverse.argtypes = C.c_int, [C.c_int, p, p]
         L.oracle_hs.restype, L.oracle_hs.argtypes = C.c_int, [C.c_int, p, p, p, p, p, p, p, p]
+        L.oracle_hs_trace.restype = C.c_int
+        L.oracle_hs_trace.argtypes = [C.c_int, p, p, p, p, p, p]
         L.oracle_solve.restype = C.c_int
         L.oracle_solve.argtypes = [C.c_int, p, p, p, p, p, d, i64, i32, i32, d, d,
                                    p, p, p, i64, p, p, C.c_int, C.c_uint64]
@@ -139,6 +141,16 @@ def hs(s, lo, hi):
     st = lib().oracle_hs(s.n, _ptr(to), _ptr(ex), _ptr(co), _ptr(lo), _ptr(hi), _ptr(olo), _ptr(ohi),
                          C.byref(u))
     return st, olo, ohi, bool(u.value)
+
+
+def hs_trace(s, lo, hi):
+    """Intermediates of one contraction step (layout: see oracle_hs_trace)."""
+    to, ex, co = _sys_arrays(s)
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    tr = np.zeros(6 * s.n * s.n + 8 * s.n + 4)
+    st = lib().oracle_hs_trace(s.n, _ptr(to), _ptr(ex), _ptr(co), _ptr(lo), _ptr(hi), _ptr(tr))
+    return st, tr
 
 
 @dataclass

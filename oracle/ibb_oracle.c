@@ -400,6 +400,19 @@ int oracle_fp32_inverse(int n, const float* Min, float* Y) {
 /* ------------------------------------------------------------------------- */
 /* Hansen-Sengupta step on one box: eq (13)-(22), Alg. 3, Alg. 4.              */
 /* ------------------------------------------------------------------------- */
+/* Optional trace of one contraction step (same layout as the device
+ * diagnostic dump), written when non-null.  Test infrastructure only. */
+static double* g_trace = NULL;
+static int tr_J(int n) { (void)n; return 0; }
+static int tr_F(int n) { return 2 * n * n; }
+static int tr_M(int n) { return 2 * n * n + 2 * n; }
+static int tr_Y(int n) { return 3 * n * n + 2 * n; }
+static int tr_g(int n) { return 4 * n * n + 2 * n; }
+static int tr_P(int n) { return 4 * n * n + 4 * n; }
+static int tr_N(int n) { return 6 * n * n + 4 * n; }
+static int tr_X(int n) { return 6 * n * n + 6 * n; }
+static int tr_flags(int n) { return 6 * n * n + 8 * n; }
+
 #define HS_EMPTY 0   /* the box holds no root */
 #define HS_SKIPPED 1 /* preconditioner unusable: box unchanged, nothing proven */
 #define HS_DONE 2    /* contracted box X' (possibly equal to X) */
@@ -423,6 +436,16 @@ static int hs_step(const osys* s, const ival* X, ival* Xn, int* unique) {
   for (int i = 0; i < n; ++i)
     for (int k = 0; k < n; ++k) J[i][k] = eval_df(s, i, k, X);
   for (int i = 0; i < n; ++i) Fc[i] = eval_f(s, i, Xc);
+  if (g_trace) {
+    for (int i = 0; i < n; ++i) {
+      for (int k = 0; k < n; ++k) {
+        g_trace[tr_J(n) + (i * n + k) * 2] = J[i][k].lo;
+        g_trace[tr_J(n) + (i * n + k) * 2 + 1] = J[i][k].hi;
+      }
+      g_trace[tr_F(n) + 2 * i] = Fc[i].lo;
+      g_trace[tr_F(n) + 2 * i + 1] = Fc[i].hi;
+    }
+  }
 
   /* B ~ inverse of mid J(X), single precision (narrowing rounds to nearest) */
   for (int i = 0; i < n; ++i)
@@ -431,7 +454,14 @@ static int hs_step(const osys* s, const ival* X, ival* Xn, int* unique) {
       fesetround(FE_TONEAREST);
       Mf[i * n + k] = (float)m;
     }
-  if (oracle_fp32_inverse(n, Mf, Yf) != 0) return HS_SKIPPED;
+  if (g_trace)
+    for (int i = 0; i < n * n; ++i) g_trace[tr_M(n) + i] = (double)Mf[i];
+  if (oracle_fp32_inverse(n, Mf, Yf) != 0) {
+    if (g_trace) g_trace[tr_flags(n)] = 1.0;
+    return HS_SKIPPED;
+  }
+  if (g_trace)
+    for (int i = 0; i < n * n; ++i) g_trace[tr_Y(n) + i] = (double)Yf[i];
 
   /* g = B F(x) and P = B J(X) by interval matrix products (Alg. 4): the sum
    * over k ascending, starting from the first term.  Terms whose point or
@@ -461,6 +491,15 @@ static int hs_step(const osys* s, const ival* X, ival* Xn, int* unique) {
     }
   }
 
+  if (g_trace)
+    for (int i = 0; i < n; ++i) {
+      g_trace[tr_g(n) + 2 * i] = g[i].lo;
+      g_trace[tr_g(n) + 2 * i + 1] = g[i].hi;
+      for (int j = 0; j < n; ++j) {
+        g_trace[tr_P(n) + (i * n + j) * 2] = P[i][j].lo;
+        g_trace[tr_P(n) + (i * n + j) * 2 + 1] = P[i][j].hi;
+      }
+    }
   /* X - x, eq (19) */
   for (int k = 0; k < n; ++k) D[k] = i_sub(X[k], Xc[k]);
 
@@ -490,6 +529,10 @@ static int hs_step(const osys* s, const ival* X, ival* Xn, int* unique) {
     }
     if (have) N = i_add(N, upper);
 
+    if (g_trace) {
+      g_trace[tr_N(n) + 2 * i] = N.lo;
+      g_trace[tr_N(n) + 2 * i + 1] = N.hi;
+    }
     ival Q[2];
     int nq = i_div_ext(N, P[i][i], Q);
     /* Y_i = x_i - Q, piece by piece; X'_i = hull of (piece intersect X_i) */
@@ -511,13 +554,39 @@ static int hs_step(const osys* s, const ival* X, ival* Xn, int* unique) {
         nhi = max2(nhi, b);
       }
     }
-    if (!any) return HS_EMPTY;
+    if (!any) {
+      if (g_trace) g_trace[tr_flags(n) + 1] = 1.0;
+      return HS_EMPTY;
+    }
     uniq = uniq && inside;
     Xn[i] = iv(nlo, nhi);
+    if (g_trace) {
+      g_trace[tr_X(n) + 2 * i] = nlo;
+      g_trace[tr_X(n) + 2 * i + 1] = nhi;
+    }
     Dn[i] = i_sub(Xn[i], Xc[i]);
   }
   *unique = uniq;
+  if (g_trace) {
+    g_trace[tr_flags(n) + 2] = uniq ? 1.0 : 0.0;
+    g_trace[tr_flags(n) + 3] = 1.0;
+  }
   return HS_DONE;
+}
+
+/* One contraction step with its intermediates written to `trace`
+ * (6n^2 + 8n + 4 doubles, layout of tr_* above). */
+int oracle_hs_trace(int n, const int32_t* term_off, const uint8_t* expo, const double* coef,
+                    const double* lo, const double* hi, double* trace) {
+  osys s = make_sys(n, term_off, expo, coef);
+  ival X[OR_MAX_N], Xn[OR_MAX_N];
+  for (int k = 0; k < n; ++k) X[k] = iv(lo[k], hi[k]);
+  memset(trace, 0, sizeof(double) * (size_t)(6 * n * n + 8 * n + 4));
+  int u = 0;
+  g_trace = trace;
+  int st = hs_step(&s, X, Xn, &u);
+  g_trace = NULL;
+  return st;
 }
 
 int oracle_hs(int n, const int32_t* term_off, const uint8_t* expo, const double* coef,

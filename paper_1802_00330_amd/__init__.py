@@ -31,7 +31,7 @@ STATS_FIELDS = ("processed", "excluded_eval", "excluded_hs", "hs_skipped", "reco
 
 EXPORTS = ("ibb_ctx_create", "ibb_ctx_destroy", "ibb_strerror", "ibb_params_default", "ibb_solve",
            "ibb_workspace_size", "ibb_solve_async", "ibb_last_level_sizes", "ibb_last_kernel_ms",
-           "ibb_selftest_ops")
+           "ibb_selftest_ops", "ibb_debug_step", "ibb_solve_batch")
 
 
 class IbbSystem(C.Structure):
@@ -79,6 +79,10 @@ def load_library(path: str = LIB_PATH):
     L.ibb_last_level_sizes.restype, L.ibb_last_level_sizes.argtypes = i64, [p, p, i64]
     L.ibb_selftest_ops.restype, L.ibb_selftest_ops.argtypes = C.c_int, [p, i32, i64, p, p, p]
     L.ibb_last_kernel_ms.restype, L.ibb_last_kernel_ms.argtypes = C.c_double, [p]
+    L.ibb_solve_batch.restype = C.c_int
+    L.ibb_solve_batch.argtypes = [p, i32, p, p, p, p, p, p, p, i64, p, p, p]
+    L.ibb_debug_step.restype = C.c_int
+    L.ibb_debug_step.argtypes = [p, C.POINTER(IbbSystem), p, p, C.POINTER(IbbParams), p, i64]
     _lib = L
     return L
 
@@ -254,3 +258,57 @@ def ibb_selftest_ops(ctx: Context, op: int, a: np.ndarray, b: np.ndarray) -> np.
     if st != OK:
         raise RuntimeError(f"ibb_selftest_ops: {ibb_strerror(st)}")
     return out
+
+
+def dbg_len(n: int) -> int:
+    return 6 * n * n + 8 * n + 4
+
+
+def ibb_debug_step(ctx: Context, s, lo, hi, params: Optional[IbbParams] = None) -> np.ndarray:
+    """Intermediates of the device step on one box (see include/ibb.h)."""
+    ref = _SysRef(s)
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    params = params or make_params(s.tol)
+    dump = np.zeros(dbg_len(s.n))
+    st = load_library().ibb_debug_step(ctx.handle, C.byref(ref.c), _ptr(lo), _ptr(hi), C.byref(params),
+                                       _ptr(dump), int(dump.size))
+    if st != OK:
+        raise RuntimeError(f"ibb_debug_step: {ibb_strerror(st)}")
+    return dump
+
+
+def ibb_solve_batch(ctx: Context, systems, params=None, cap: int = 1 << 16):
+    """Solve many systems in one pass; returns a list of Result (one per system)."""
+    L = load_library()
+    B = len(systems)
+    refs = [_SysRef(s) for s in systems]
+    arr = (IbbSystem * B)(*[r.c for r in refs])
+    lo = np.zeros((B, MAX_N))
+    hi = np.zeros((B, MAX_N))
+    for b, s in enumerate(systems):
+        lo[b, :s.n] = s.lo
+        hi[b, :s.n] = s.hi
+    if params is None:
+        params = [make_params(s.tol) for s in systems]
+    parr = (IbbParams * B)(*params)
+    while True:
+        olo = np.zeros((max(cap, 1), MAX_N))
+        ohi = np.zeros((max(cap, 1), MAX_N))
+        otag = np.zeros(max(cap, 1), dtype=np.uint8)
+        off = np.zeros(B + 1, dtype=np.int64)
+        status = np.zeros(B, dtype=np.int32)
+        stats = (IbbStats * B)()
+        st = L.ibb_solve_batch(ctx.handle, int(B), arr, _ptr(lo), _ptr(hi), parr, _ptr(olo), _ptr(ohi), _ptr(otag),
+                               int(cap), _ptr(off), _ptr(status), stats)
+        if st == ERR_OUTPUT_CAPACITY:
+            cap = int(off[-1])
+            continue
+        if st != OK:
+            raise RuntimeError(f"ibb_solve_batch: {ibb_strerror(st)}")
+        out = []
+        for b, s in enumerate(systems):
+            a, e = int(off[b]), int(off[b + 1])
+            sd = {f: int(getattr(stats[b], f)) for f in STATS_FIELDS}
+            out.append(Result(int(status[b]), olo[a:e, :s.n].copy(), ohi[a:e, :s.n].copy(), otag[a:e].copy(), sd))
+        return out

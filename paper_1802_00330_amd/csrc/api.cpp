@@ -14,7 +14,14 @@
 namespace ibb {
 // kernels.hip
 size_t scratch_bytes(int G);
-const void* solve_kernel_ptr(int G);
+const void* solve_kernel_ptr(int G, bool multi);
+hipError_t launch_prep(hipStream_t s, uint64_t* blobs, const long long* blob_off, int B);
+hipError_t launch_batch_init(hipStream_t s, Ctrl* c, double* front0, uint32_t* meta0, uint32_t* sys0,
+                             const double* lo, const double* hi, const int* bucket, int m, int G, const int* nsys,
+                             unsigned long long* count_sys, int B);
+hipError_t launch_seg_sort(hipStream_t s, const double* box, const uint32_t* tag, const uint32_t* out_sys,
+                           long long M, const long long* seg_off, unsigned long long* cursor, uint32_t* order,
+                           const int* nsys, double* out_lo, double* out_hi, uint8_t* out_tag);
 hipError_t launch_init(hipStream_t s, Ctrl* c, double* front0, uint32_t* meta0, const double* lo,
                        const double* hi, int n, int G);
 hipError_t launch_sort(hipStream_t s, const double* box, const uint32_t* tag, const Ctrl* c, int n, int G,
@@ -137,6 +144,8 @@ void compile(const ibb_system* s, Compiled& c) {
   w += words(sizeof(uint32_t) * TD);
   d.dfac_w = w;
   w += TD;
+  d.dco_w = w;
+  w += 2 * TD;
   d.total_w = w;
   std::memcpy(d.jnz, jnz, sizeof jnz);
 
@@ -187,7 +196,7 @@ WsLayout ws_layout(int n, size_t blob_words, long long frontier_cap, long long o
 // Upper bound of the system blob size for a given n (IBB_MAX_TERMS terms).
 size_t max_blob_words(int n) {
   const size_t T = IBB_MAX_TERMS, TD = (size_t)IBB_MAX_TERMS * IBB_MAX_DEG;
-  return sizeof(SysDesc) / 8 + (n + 2) / 2 + (n * n + 2) / 2 + 2 * T + 2 * TD + (TD + 1) / 2 + 8;
+  return sizeof(SysDesc) / 8 + (n + 2) / 2 + (n * n + 2) / 2 + 2 * T + 4 * TD + (TD + 1) / 2 + 8;
 }
 
 }  // namespace
@@ -209,6 +218,8 @@ struct ibb_ctx {
   char* pinned = nullptr;  // host staging of the inputs
   size_t pinned_bytes = 0;
   std::vector<long long> last_levels;
+  void* bws = nullptr;  // batch workspace
+  size_t bws_bytes = 0;
 };
 
 namespace {
@@ -243,11 +254,30 @@ int ensure_pinned(ibb_ctx* ctx, size_t need) {
   return IBB_OK;
 }
 
+// Launch geometry of a persistent kernel: waves per block, LDS, grid.
+int persistent_geometry(ibb_ctx* ctx, const void* fn, size_t table_bytes, int G, int* waves_out,
+                        size_t* lds_out, int* blocks_out) {
+  const size_t per_wave = scratch_bytes(G);
+  int waves = 4;
+  while (waves > 1 && table_bytes + per_wave * waves > ctx->max_lds_block) --waves;
+  const size_t lds = table_bytes + per_wave * waves;
+  if (lds > ctx->max_lds_block) return IBB_ERR_UNSUPPORTED;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return IBB_ERR_DEVICE;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * waves, lds) != hipSuccess || per_cu < 1)
+    return IBB_ERR_UNSUPPORTED;
+  *waves_out = waves;
+  *lds_out = lds;
+  *blocks_out = per_cu * ctx->num_cu;
+  return IBB_OK;
+}
+
 // Enqueue one solve into a partitioned workspace; outputs to device arrays.
 int enqueue_solve(ibb_ctx* ctx, const Compiled& c, const double* lo, const double* hi,
                   const ibb_params* p, char* ws, const WsLayout& L, long long frontier_cap,
                   long long out_cap, double* d_out_lo, double* d_out_hi, uint8_t* d_out_tag,
-                  long long* d_info, hipStream_t s) {
+                  long long* d_info, hipStream_t s, int max_levels = 0, double* d_dbg = nullptr) {
   const int n = c.n, G = c.G;
   // stage the host inputs: blob, lo, hi
   const size_t blob_bytes = 8 * c.blob.size();
@@ -264,6 +294,7 @@ int enqueue_solve(ibb_ctx* ctx, const Compiled& c, const double* lo, const doubl
   hipEventRecord(ctx->staged, s);
   ctx->staged_pending = true;
 
+  if (launch_prep(s, reinterpret_cast<uint64_t*>(ws + L.blob), nullptr, 1) != hipSuccess) return IBB_ERR_DEVICE;
   Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
   const double* dlo = reinterpret_cast<const double*>(ws + L.box);
   if (launch_init(s, ctrl, reinterpret_cast<double*>(ws + L.front0), reinterpret_cast<uint32_t*>(ws + L.meta0),
@@ -291,20 +322,19 @@ int enqueue_solve(ibb_ctx* ctx, const Compiled& c, const double* lo, const doubl
   a.split_mode = p->split_mode;
   a.max_rc = p->max_recontract;
   a.timeout_ticks = ctx->clock_khz * 1000LL * 20;  // 20 s per barrier wait
+  a.max_levels = max_levels;
+  a.dbg = d_dbg;
+  a.out_count = &ctrl->out_count;
+  a.out_stride = G;
 
-  const void* fn = solve_kernel_ptr(G);
+  const void* fn = solve_kernel_ptr(G, false);
   const size_t tbytes = (table_lds_bytes(n, c.T, c.TD) + 15) & ~size_t(15);
-  const size_t per_wave = scratch_bytes(G);
-  int waves = 4;
-  while (waves > 1 && tbytes + per_wave * waves > ctx->max_lds_block) --waves;
-  const size_t lds = tbytes + per_wave * waves;
-  if (lds > ctx->max_lds_block) return IBB_ERR_UNSUPPORTED;
-  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-    return IBB_ERR_DEVICE;
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * waves, lds) != hipSuccess || per_cu < 1)
-    return IBB_ERR_UNSUPPORTED;
-  const int blocks = per_cu * ctx->num_cu;
+  int waves = 0, blocks = 0;
+  size_t lds = 0;
+  {
+    const int gst = persistent_geometry(ctx, fn, tbytes, G, &waves, &lds, &blocks);
+    if (gst) return gst;
+  }
   a.nblocks = blocks;
   void* args[] = {&a};
   hipEventRecord(ctx->ev0, s);
@@ -335,6 +365,265 @@ void fill_stats(ibb_stats* st, const long long* info, double ms) {
 }
 
 }  // namespace
+
+
+// ---------------------------------------------------------------------------
+// Batches: many systems per launch.  Systems are bucketed by lanes per box
+// (2, 4, 8, 16); each bucket is one persistent launch over a frontier whose
+// records carry their system index; tables are read from global memory.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BatchLayout {
+  size_t blobs, boff, sp, nsys, lo, hi, count_sys, cum_sys, status_sys, stats_sys, bucket, ctrl, level, front0,
+      front1, meta0, meta1, sys0, sys1, out_box, out_tag, out_sys, out_count, seg_off, cursor, order, s_lo, s_hi,
+      s_tag, total;
+};
+
+BatchLayout batch_layout(int B, size_t blob_words, long long fcap, long long ocap) {
+  BatchLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = round_up(o + bytes, 256);
+    return at;
+  };
+  L.blobs = take(8 * blob_words);
+  L.boff = take(sizeof(long long) * B);
+  L.sp = take(sizeof(SysParams) * B);
+  L.nsys = take(sizeof(int) * B);
+  L.lo = take(sizeof(double) * kMaxN * B);
+  L.hi = take(sizeof(double) * kMaxN * B);
+  L.count_sys = take(sizeof(unsigned long long) * 3 * B);
+  L.cum_sys = take(sizeof(unsigned long long) * 2 * B);
+  L.status_sys = take(sizeof(int) * B);
+  L.stats_sys = take(sizeof(unsigned long long) * 8 * B);
+  L.bucket = take(sizeof(int) * B);
+  L.ctrl = take(sizeof(Ctrl) * 4);
+  L.level = take(sizeof(long long) * kLevelCap);
+  L.front0 = take(sizeof(double) * 2 * kMaxN * (size_t)fcap);
+  L.front1 = take(sizeof(double) * 2 * kMaxN * (size_t)fcap);
+  L.meta0 = take(sizeof(uint32_t) * (size_t)fcap);
+  L.meta1 = take(sizeof(uint32_t) * (size_t)fcap);
+  L.sys0 = take(sizeof(uint32_t) * (size_t)fcap);
+  L.sys1 = take(sizeof(uint32_t) * (size_t)fcap);
+  L.out_box = take(sizeof(double) * 2 * kMaxN * (size_t)ocap);
+  L.out_tag = take(sizeof(uint32_t) * (size_t)ocap);
+  L.out_sys = take(sizeof(uint32_t) * (size_t)ocap);
+  L.out_count = take(sizeof(unsigned long long));
+  L.seg_off = take(sizeof(long long) * (B + 1));
+  L.cursor = take(sizeof(unsigned long long) * B);
+  L.order = take(sizeof(uint32_t) * (size_t)ocap);
+  L.s_lo = take(sizeof(double) * kMaxN * (size_t)ocap);
+  L.s_hi = take(sizeof(double) * kMaxN * (size_t)ocap);
+  L.s_tag = take((size_t)ocap);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+extern "C" int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const double* lo,
+                               const double* hi, const ibb_params* params, double* out_lo, double* out_hi,
+                               uint8_t* out_tag, int64_t cap, int64_t* out_off, int32_t* status,
+                               ibb_stats* stats) {
+  if (!ctx || B < 1 || !systems || !lo || !hi || !params || !out_off || !status || cap < 0 ||
+      (cap > 0 && (!out_lo || !out_hi || !out_tag)))
+    return IBB_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return IBB_ERR_DEVICE;
+  std::vector<Compiled> comp((size_t)B);
+  std::vector<long long> boff((size_t)B, 0);
+  std::vector<int> nsys((size_t)B, 1);
+  std::vector<SysParams> sp((size_t)B);
+  std::vector<int> buckets[5];
+  size_t words = 0;
+  long long first_valid = -1;
+  for (int b = 0; b < B; ++b) {
+    status[b] = validate(&systems[b], lo + (size_t)b * kMaxN, hi + (size_t)b * kMaxN, &params[b]);
+    if (status[b] != IBB_OK) continue;
+    try {
+      compile(&systems[b], comp[b]);
+    } catch (...) {
+      return IBB_ERR_NO_MEMORY;
+    }
+    boff[b] = (long long)words;
+    if (first_valid < 0) first_valid = (long long)words;
+    words += comp[b].blob.size();
+    nsys[b] = comp[b].n;
+    const ibb_params& p = params[b];
+    sp[b] = SysParams{p.tol, p.recontract_ratio, p.hs_max_width, p.max_boxes, p.split_mode, p.max_recontract};
+    const int G = comp[b].G;
+    buckets[G == 2 ? 0 : G == 4 ? 1 : G == 8 ? 2 : 3].push_back(b);
+  }
+  if (first_valid < 0) {
+    for (int b = 0; b <= B; ++b) out_off[b] = 0;
+    return IBB_OK;
+  }
+  for (int b = 0; b < B; ++b)
+    if (status[b] != IBB_OK) boff[b] = first_valid;  // never stepped; any valid table
+  std::vector<uint64_t> blob(words);
+  for (int b = 0; b < B; ++b)
+    if (status[b] == IBB_OK) std::memcpy(blob.data() + boff[b], comp[b].blob.data(), 8 * comp[b].blob.size());
+  std::vector<double> lo16((size_t)B * kMaxN, 0.0), hi16((size_t)B * kMaxN, 0.0);
+  for (int b = 0; b < B; ++b)
+    for (int k = 0; k < nsys[b]; ++k) {
+      lo16[(size_t)b * kMaxN + k] = lo[(size_t)b * kMaxN + k];
+      hi16[(size_t)b * kMaxN + k] = hi[(size_t)b * kMaxN + k];
+    }
+  std::vector<int> bucket_list;
+  int bucket_start[5] = {0};
+  for (int q = 0; q < 4; ++q) {
+    bucket_start[q] = (int)bucket_list.size();
+    bucket_list.insert(bucket_list.end(), buckets[q].begin(), buckets[q].end());
+  }
+  bucket_start[4] = (int)bucket_list.size();
+
+  long long fcap = 1LL << 20, ocap = 1LL << 14;
+  hipStream_t s = ctx->stream;
+  for (int attempt = 0; attempt < 10; ++attempt) {
+    const BatchLayout L = batch_layout(B, words, fcap, ocap);
+    int st = ensure_device(&ctx->bws, &ctx->bws_bytes, L.total);
+    if (st) return st;
+    char* w = static_cast<char*>(ctx->bws);
+    auto D = [&](size_t off) { return w + off; };
+    if (hipMemcpyAsync(D(L.blobs), blob.data(), 8 * words, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(D(L.boff), boff.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(D(L.sp), sp.data(), sizeof(SysParams) * B, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(D(L.nsys), nsys.data(), sizeof(int) * B, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(D(L.lo), lo16.data(), sizeof(double) * kMaxN * B, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(D(L.hi), hi16.data(), sizeof(double) * kMaxN * B, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(D(L.bucket), bucket_list.data(), sizeof(int) * bucket_list.size(), hipMemcpyHostToDevice,
+                       s) != hipSuccess ||
+        hipMemsetAsync(D(L.count_sys), 0, L.ctrl - L.count_sys, s) != hipSuccess ||
+        hipMemsetAsync(D(L.out_count), 0, L.order - L.out_count, s) != hipSuccess)
+      return IBB_ERR_DEVICE;
+    if (launch_prep(s, reinterpret_cast<uint64_t*>(D(L.blobs)), reinterpret_cast<const long long*>(D(L.boff)),
+                    B) != hipSuccess)
+      return IBB_ERR_DEVICE;
+    hipEventRecord(ctx->ev0, s);
+    for (int q = 0; q < 4; ++q) {
+      const int m = bucket_start[q + 1] - bucket_start[q];
+      if (m == 0) continue;
+      const int G = 2 << q;
+      Ctrl* ctrl = reinterpret_cast<Ctrl*>(D(L.ctrl)) + q;
+      if (launch_batch_init(s, ctrl, reinterpret_cast<double*>(D(L.front0)), reinterpret_cast<uint32_t*>(D(L.meta0)),
+                            reinterpret_cast<uint32_t*>(D(L.sys0)), reinterpret_cast<const double*>(D(L.lo)),
+                            reinterpret_cast<const double*>(D(L.hi)),
+                            reinterpret_cast<const int*>(D(L.bucket)) + bucket_start[q], m, G,
+                            reinterpret_cast<const int*>(D(L.nsys)),
+                            reinterpret_cast<unsigned long long*>(D(L.count_sys)), B) != hipSuccess)
+        return IBB_ERR_DEVICE;
+      SolveArgs a;
+      std::memset(&a, 0, sizeof a);
+      a.front[0] = reinterpret_cast<double*>(D(L.front0));
+      a.front[1] = reinterpret_cast<double*>(D(L.front1));
+      a.meta[0] = reinterpret_cast<uint32_t*>(D(L.meta0));
+      a.meta[1] = reinterpret_cast<uint32_t*>(D(L.meta1));
+      a.sys[0] = reinterpret_cast<uint32_t*>(D(L.sys0));
+      a.sys[1] = reinterpret_cast<uint32_t*>(D(L.sys1));
+      a.front_cap = fcap;
+      a.out_box = reinterpret_cast<double*>(D(L.out_box));
+      a.out_tag = reinterpret_cast<uint32_t*>(D(L.out_tag));
+      a.out_sys = reinterpret_cast<uint32_t*>(D(L.out_sys));
+      a.out_cap = ocap;
+      a.out_count = reinterpret_cast<unsigned long long*>(D(L.out_count));
+      a.out_stride = kMaxN;
+      a.ctrl = ctrl;
+      a.level_sizes = reinterpret_cast<long long*>(D(L.level));
+      a.level_cap = kLevelCap;
+      a.max_boxes = 1LL << 62;
+      a.timeout_ticks = ctx->clock_khz * 1000LL * 20;
+      a.blobs = reinterpret_cast<const uint64_t*>(D(L.blobs));
+      a.blob_off = reinterpret_cast<const long long*>(D(L.boff));
+      a.sp = reinterpret_cast<const SysParams*>(D(L.sp));
+      a.count_sys = reinterpret_cast<unsigned long long*>(D(L.count_sys));
+      a.cum_sys = reinterpret_cast<unsigned long long*>(D(L.cum_sys));
+      a.status_sys = reinterpret_cast<int*>(D(L.status_sys));
+      a.stats_sys = reinterpret_cast<unsigned long long*>(D(L.stats_sys));
+      a.B = B;
+      const void* fn = solve_kernel_ptr(G, true);
+      int waves = 0, blocks = 0;
+      size_t lds = 0;
+      st = persistent_geometry(ctx, fn, 0, G, &waves, &lds, &blocks);
+      if (st) return st;
+      a.nblocks = blocks;
+      void* args[] = {&a};
+      if (hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(64 * waves), args, (unsigned)lds, s) != hipSuccess)
+        return IBB_ERR_DEVICE;
+    }
+    hipEventRecord(ctx->ev1, s);
+    ctx->timed_pending = true;
+    Ctrl ctrls[4];
+    unsigned long long M = 0;
+    if (hipMemcpyAsync(ctrls, D(L.ctrl), sizeof ctrls, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&M, D(L.out_count), sizeof M, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return IBB_ERR_DEVICE;
+    bool overflow = false;
+    for (int q = 0; q < 4; ++q) {
+      if (bucket_start[q + 1] == bucket_start[q]) continue;
+      if (ctrls[q].status == IBB_ERR_QUEUE_OVERFLOW) overflow = true;
+      else if (ctrls[q].status != 0) return ctrls[q].status;
+    }
+    if (overflow) {
+      fcap *= 4;
+      continue;
+    }
+    if ((long long)M > ocap) {
+      ocap = (long long)M;
+      continue;
+    }
+    std::vector<int> sst((size_t)B);
+    std::vector<unsigned long long> sstats((size_t)B * 8);
+    if (hipMemcpy(sst.data(), D(L.status_sys), sizeof(int) * B, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(sstats.data(), D(L.stats_sys), sizeof(unsigned long long) * 8 * B, hipMemcpyDeviceToHost) !=
+            hipSuccess)
+      return IBB_ERR_DEVICE;
+    // per-system output segments (boxes of failed systems are not returned)
+    std::vector<long long> seg((size_t)B + 1, 0);
+    for (int b = 0; b < B; ++b) {
+      if (status[b] == IBB_OK && sst[b] != 0) status[b] = sst[b];
+      const long long mb = (long long)(sstats[(size_t)b * 8 + 6] + sstats[(size_t)b * 8 + 7]);
+      seg[b + 1] = seg[b] + mb;
+      if (stats) {
+        ibb_stats& o = stats[b];
+        std::memset(&o, 0, sizeof o);
+        int64_t* f = &o.processed;
+        for (int k = 0; k < 8; ++k) f[k] = (int64_t)sstats[(size_t)b * 8 + k];
+      }
+    }
+    if (seg[B] != (long long)M) return IBB_ERR_DEVICE;  // counters disagree with the output list
+    // result offsets: failed systems contribute no boxes
+    out_off[0] = 0;
+    for (int b = 0; b < B; ++b) out_off[b + 1] = out_off[b] + (status[b] == IBB_OK ? seg[b + 1] - seg[b] : 0);
+    if (hipMemcpyAsync(D(L.seg_off), seg.data(), sizeof(long long) * (B + 1), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        launch_seg_sort(s, reinterpret_cast<const double*>(D(L.out_box)), reinterpret_cast<const uint32_t*>(D(L.out_tag)),
+                        reinterpret_cast<const uint32_t*>(D(L.out_sys)), (long long)M,
+                        reinterpret_cast<const long long*>(D(L.seg_off)),
+                        reinterpret_cast<unsigned long long*>(D(L.cursor)), reinterpret_cast<uint32_t*>(D(L.order)),
+                        reinterpret_cast<const int*>(D(L.nsys)), reinterpret_cast<double*>(D(L.s_lo)),
+                        reinterpret_cast<double*>(D(L.s_hi)), reinterpret_cast<uint8_t*>(D(L.s_tag))) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return IBB_ERR_DEVICE;
+    if (out_off[B] > cap) return IBB_ERR_OUTPUT_CAPACITY;
+    // copy each successful system's segment
+    for (int b = 0; b < B; ++b) {
+      if (status[b] != IBB_OK) continue;
+      const long long m = seg[b + 1] - seg[b];
+      if (m == 0) continue;
+      const size_t src = (size_t)seg[b], dst = (size_t)out_off[b];
+      if (hipMemcpy(out_lo + dst * kMaxN, D(L.s_lo) + src * kMaxN * sizeof(double), sizeof(double) * kMaxN * m,
+                    hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(out_hi + dst * kMaxN, D(L.s_hi) + src * kMaxN * sizeof(double), sizeof(double) * kMaxN * m,
+                    hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(out_tag + dst, D(L.s_tag) + src, (size_t)m, hipMemcpyDeviceToHost) != hipSuccess)
+        return IBB_ERR_DEVICE;
+    }
+    return IBB_OK;
+  }
+  return IBB_ERR_NO_MEMORY;
+}
 
 extern "C" {
 
@@ -398,6 +687,7 @@ void ibb_ctx_destroy(ibb_ctx* c) {
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream);
   if (c->ws) hipFree(c->ws);
+  if (c->bws) hipFree(c->bws);
   if (c->sorted) hipFree(c->sorted);
   if (c->info) hipFree(c->info);
   if (c->pinned) hipHostFree(c->pinned);
@@ -515,6 +805,43 @@ int64_t ibb_last_level_sizes(ibb_ctx* ctx, int64_t* sizes, int64_t cap) {
   const int64_t m = (int64_t)ctx->last_levels.size();
   for (int64_t i = 0; i < std::min(m, cap); ++i) sizes[i] = ctx->last_levels[(size_t)i];
   return m;
+}
+
+int ibb_debug_step(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const double* hi,
+                   const ibb_params* params, double* dump, int64_t dump_len) {
+  if (!ctx || !dump) return IBB_ERR_INVALID_ARG;
+  int st = validate(sys, lo, hi, params);
+  if (st) return st;
+  const int n = sys->n;
+  if (dump_len < dbg_len(n)) return IBB_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return IBB_ERR_DEVICE;
+  Compiled c;
+  try {
+    compile(sys, c);
+  } catch (...) {
+    return IBB_ERR_NO_MEMORY;
+  }
+  const long long fcap = 1 << 17, ocap = 1 << 10;
+  const WsLayout L = ws_layout(n, c.blob.size(), fcap, ocap);
+  const size_t sorted_need = (size_t)ocap * (2 * n * sizeof(double) + 1) + 64;
+  st = ensure_device(&ctx->ws, &ctx->ws_bytes, L.total);
+  if (!st) st = ensure_device(reinterpret_cast<void**>(&ctx->sorted), &ctx->sorted_bytes, sorted_need);
+  if (st) return st;
+  double* d_dbg = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&d_dbg), sizeof(double) * dbg_len(n)) != hipSuccess) return IBB_ERR_NO_MEMORY;
+  st = IBB_OK;
+  if (hipMemsetAsync(d_dbg, 0, sizeof(double) * dbg_len(n), ctx->stream) != hipSuccess) st = IBB_ERR_DEVICE;
+  double* d_lo = ctx->sorted;
+  double* d_hi = d_lo + (size_t)ocap * n;
+  uint8_t* d_tag = reinterpret_cast<uint8_t*>(d_hi + (size_t)ocap * n);
+  if (!st)
+    st = enqueue_solve(ctx, c, lo, hi, params, static_cast<char*>(ctx->ws), L, fcap, ocap, d_lo, d_hi, d_tag,
+                       ctx->info, ctx->stream, 1, d_dbg);
+  if (!st && (hipStreamSynchronize(ctx->stream) != hipSuccess ||
+              hipMemcpy(dump, d_dbg, sizeof(double) * dbg_len(n), hipMemcpyDeviceToHost) != hipSuccess))
+    st = IBB_ERR_DEVICE;
+  hipFree(d_dbg);
+  return st;
 }
 
 int ibb_selftest_ops(ibb_ctx* ctx, int32_t op, int64_t n, const double* a, const double* b, double* out) {

@@ -12,6 +12,8 @@
 // preconditioner at its logical pivot position.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "interval.hpp"
 #include "layout.hpp"
 
@@ -103,8 +105,7 @@ __device__ LTable stage_table(const uint64_t* blob, char* lds) {
   const int* g_der = reinterpret_cast<const int*>(blob + d->der_off_w);
   const double* g_coef = reinterpret_cast<const double*>(blob + d->coef_w);
   const uint64_t* g_fac = blob + d->fac_w;
-  const double* g_dcoef = reinterpret_cast<const double*>(blob + d->dcoef_w);
-  const uint32_t* g_dmult = reinterpret_cast<const uint32_t*>(blob + d->dmult_w);
+  const iv* g_dco = reinterpret_cast<const iv*>(blob + d->dco_w);
   const uint64_t* g_dfac = blob + d->dfac_w;
   for (int i = threadIdx.x; i <= n; i += blockDim.x) eq_off[i] = g_eq[i];
   for (int i = threadIdx.x; i <= n * n; i += blockDim.x) der_off[i] = g_der[i];
@@ -114,13 +115,42 @@ __device__ LTable stage_table(const uint64_t* blob, char* lds) {
     fac[i] = g_fac[i];
   }
   for (int i = threadIdx.x; i < TD; i += blockDim.x) {
-    // derivative coefficient e_k * c, enclosed (both bounds rounded outward)
-    double e = (double)g_dmult[i];
-    double c = g_dcoef[i];
-    dco[i] = iv{rmul(e, c), rmul_neg(e, c)};
+    dco[i] = g_dco[i];
     dfac[i] = g_dfac[i];
   }
   return LTable{n, eq_off, der_off, jnz, coef, fac, dco, dfac};
+}
+
+// The same table read in place from global memory (batches of systems).
+__device__ __forceinline__ LTable global_table(const uint64_t* blob) {
+  const SysDesc* d = reinterpret_cast<const SysDesc*>(blob);
+  return LTable{d->n,
+                reinterpret_cast<const int*>(blob + d->eq_off_w),
+                reinterpret_cast<const int*>(blob + d->der_off_w),
+                d->jnz,
+                reinterpret_cast<const double*>(blob + d->coef_w),
+                blob + d->fac_w,
+                reinterpret_cast<const iv*>(blob + d->dco_w),
+                blob + d->dfac_w};
+}
+
+// Encloses every derivative coefficient e_k * c once per system:
+// [R(e c), -R(-e c)], written into the blob's dco region.
+__global__ void prep_kernel(uint64_t* blobs, const long long* blob_off, int B) {
+  set_fp64_round_down();
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    uint64_t* blob = blobs + (blob_off ? blob_off[b] : 0);
+    const SysDesc* d = reinterpret_cast<const SysDesc*>(blob);
+    const double* dcoef = reinterpret_cast<const double*>(blob + d->dcoef_w);
+    const uint32_t* dmult = reinterpret_cast<const uint32_t*>(blob + d->dmult_w);
+    double* dco = reinterpret_cast<double*>(blob + d->dco_w);
+    for (int i = threadIdx.x; i < d->TD; i += blockDim.x) {
+      const double e = (double)dmult[i];
+      const double c = dcoef[i];
+      dco[2 * i] = rmul(e, c);
+      dco[2 * i + 1] = rmul_neg(e, c);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -252,17 +282,58 @@ __device__ __noinline__ bool gs_component(iv N, iv P, double xc, iv Xi, iv& Xn, 
 }
 
 // One tile: boxes [base, base + W) of the current level (those < cnt).
-template <int G>
-__device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, long long base,
-                          long long cnt, int cur, unsigned long long* next_count,
+// Adds v (counted at group leaders) to arr[system]: one atomic per wave when
+// all groups of the wave work on the same system, else one per group.
+__device__ __forceinline__ void sys_add(unsigned long long* arr, uint32_t sysid, unsigned v, bool leader) {
+  const uint32_t s0 = __shfl(sysid, 0, 64);
+  const bool same = __ballot(leader && sysid != s0) == 0;
+  if (same) {
+    const unsigned tot = __shfl(wave_inclusive_sum(leader ? v : 0u), 63, 64);
+    if (__lane_id() == 0 && tot) atomicAdd(&arr[s0], (unsigned long long)tot);
+  } else if (leader && v) {
+    atomicAdd(&arr[sysid], (unsigned long long)v);
+  }
+}
+
+template <int G, bool MULTI>
+__device__ void step_tile(const SolveArgs& a, const LTable& Tl, Scratch<G>& S, long long base,
+                          long long cnt, int cur, int level, unsigned long long* next_count,
                           StepCounters& sc) {
   const int lane = __lane_id();
   const int g = lane / G;
   const int r = lane % G;
-  const int n = T.n;
   const long long idx = base + g;
-  const bool valid = idx < cnt;
+  bool valid = idx < cnt;
+  // the group's system: its table, size and parameters
+  LTable T = Tl;
+  uint32_t sysid = 0;
+  double p_tol = a.tol, p_ratio = a.ratio, p_hsw = a.hs_max_width;
+  int p_split = a.split_mode, p_maxrc = a.max_rc;
+  if (MULTI) {
+    if (valid) sysid = a.sys[cur][idx];
+    T = global_table(a.blobs + a.blob_off[sysid]);
+    const SysParams sp = a.sp[sysid];
+    p_tol = sp.tol;
+    p_ratio = sp.ratio;
+    p_hsw = sp.hs_max_width;
+    p_split = sp.split_mode;
+    p_maxrc = sp.max_rc;
+    if (valid) {
+      // the budget is on the system's tree nodes, checked level by level
+      const unsigned long long total =
+          a.cum_sys[(size_t)((level + 1) & 1) * a.B + sysid] + a.count_sys[(size_t)(level % 3) * a.B + sysid];
+      if (total > (unsigned long long)sp.max_boxes) {
+        if (r == 0) atomicCAS(&a.status_sys[sysid], 0, -2);
+        valid = false;
+      } else if (r == 0) {
+        a.cum_sys[(size_t)(level & 1) * a.B + sysid] = total;
+        a.count_sys[(size_t)((level + 2) % 3) * a.B + sysid] = 0ull;
+      }
+    }
+  }
+  const int n = T.n;
   const bool row_ok = r < n;
+  double* const dbg = (a.dbg && idx == 0 && valid) ? a.dbg : nullptr;
 
   // ---- load the box and its record
   uint32_t meta = 0;
@@ -288,7 +359,7 @@ __device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, lo
 
   // ---- width of X
   const double w = group_max<G>((active && row_ok) ? iwidth(S.X[g][r]) : 0.0);
-  const bool do_hs = active && !(w > a.hs_max_width);
+  const bool do_hs = active && !(w > p_hsw);
 
   bool hs_empty = false, hs_unique = false, run = false;
   if (__ballot(do_hs) != 0) {
@@ -304,12 +375,25 @@ __device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, lo
     if (do_hs && row_ok) {
       for (int k = 0; k < n; ++k) S.J[g][r][k] = eval_partial(T, r, k, S.X[g]);
       S.Fc[g][r] = eval_equation(T, r, S.Xc[g]);
+      if (dbg) {
+        for (int k = 0; k < n; ++k) {
+          dbg[dbg_off_J(n) + (r * n + k) * 2] = S.J[g][r][k].lo;
+          dbg[dbg_off_J(n) + (r * n + k) * 2 + 1] = -S.J[g][r][k].nhi;
+        }
+        dbg[dbg_off_F(n) + 2 * r] = S.Fc[g][r].lo;
+        dbg[dbg_off_F(n) + 2 * r + 1] = -S.Fc[g][r].nhi;
+      }
     }
     wave_lds_sync();
     // H4: single-precision mid J, row r
     float M[G];
 #pragma unroll
     for (int k = 0; k < G; ++k) M[k] = (do_hs && row_ok && k < n) ? narrow_rn(imid(S.J[g][r][k])) : 0.0f;
+    if (dbg && row_ok) {
+#pragma unroll
+      for (int k = 0; k < G; ++k)
+        if (k < n) dbg[dbg_off_M(n) + r * n + k] = (double)M[k];
+    }
 
     // H5: LU with partial pivoting across the lanes of the group; pos is the
     // logical row this lane's data occupies after the row exchanges.
@@ -410,6 +494,12 @@ __device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, lo
     }
     const bool skip = group_bits<G>(__ballot(bad || zero_pivot), g) != 0;
     run = do_hs && !skip;
+    if (dbg && row_ok) {
+#pragma unroll
+      for (int c = 0; c < G; ++c)
+        if (c < n) dbg[dbg_off_Y(n) + pos * n + c] = (double)z[c];
+      if (r == 0) dbg[dbg_off_flags(n)] = skip ? 1.0 : 0.0;
+    }
 
     // H6, H7: this lane holds row `pos` of Y.
     //   g_pos = sum_m Y[pos][m] F_m(x),  P[pos][j] = sum_m Y[pos][m] J[m][j],
@@ -446,6 +536,17 @@ __device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, lo
         }
       }
     }
+    if (dbg && run && row_ok) {
+      dbg[dbg_off_g(n) + 2 * pos] = gv.lo;
+      dbg[dbg_off_g(n) + 2 * pos + 1] = -gv.nhi;
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        if (j < n) {
+          dbg[dbg_off_P(n) + (pos * n + j) * 2] = P[j].lo;
+          dbg[dbg_off_P(n) + (pos * n + j) * 2 + 1] = -P[j].nhi;
+        }
+      }
+    }
     // S_U = sum_{j > pos} P[pos][j] (X_j - x_j), j ascending
     iv SU{0.0, 0.0};
     bool hasU = false;
@@ -474,7 +575,8 @@ __device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, lo
     iv SL{0.0, 0.0};
     bool hasL = false;
     bool my_unique = true, my_empty = false;
-    for (int i = 0; i < n; ++i) {
+    const int nsweep = MULTI ? G : n;
+    for (int i = 0; i < nsweep; ++i) {
       if (run && row_ok && pos == i) {
         iv N = gv;
         if (hasL) N = iadd(N, SL);
@@ -486,6 +588,12 @@ __device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, lo
         my_empty = !ok;
         my_unique = ok && inside;
         if (!ok) xn = S.X[g][i];
+        if (dbg) {
+          dbg[dbg_off_N(n) + 2 * i] = N.lo;
+          dbg[dbg_off_N(n) + 2 * i + 1] = -N.nhi;
+          dbg[dbg_off_X(n) + 2 * i] = xn.lo;
+          dbg[dbg_off_X(n) + 2 * i + 1] = -xn.nhi;
+        }
         S.Xn[g][i] = xn;
         S.D[g][i] = isub(xn, point_iv(xc));
       }
@@ -498,6 +606,11 @@ __device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, lo
     }
     hs_empty = run && group_bits<G>(__ballot(my_empty), g) != 0;
     hs_unique = run && group_bits<G>(__ballot(row_ok && !my_unique), g) == 0;
+    if (dbg && r == 0) {
+      dbg[dbg_off_flags(n) + 1] = hs_empty ? 1.0 : 0.0;
+      dbg[dbg_off_flags(n) + 2] = hs_unique ? 1.0 : 0.0;
+      dbg[dbg_off_flags(n) + 3] = run ? 1.0 : 0.0;
+    }
   }
   // boxes without a contraction keep X as X'
   if (active && !run && row_ok) S.Xn[g][r] = S.X[g][r];
@@ -518,11 +631,11 @@ __device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, lo
   double mid_kk = 0.0;
   uint32_t split_mask = 0;
   if (alive) {
-    if (wn <= a.tol) {
+    if (wn <= p_tol) {
       emit = true;
       tag = prv ? 1 : 0;
     } else if (prv) {
-      if (wn < w && rc + 1 < a.max_rc) {
+      if (wn < w && rc + 1 < p_maxrc) {
         kind = 1;
         n_push = 1;
         child_meta = 1u | ((uint32_t)(rc + 1) << 8);
@@ -530,11 +643,11 @@ __device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, lo
         emit = true;
         tag = 1;
       }
-    } else if (wn <= rmul(a.ratio, w) && rc + 1 < a.max_rc) {
+    } else if (wn <= rmul(p_ratio, w) && rc + 1 < p_maxrc) {
       kind = 1;
       n_push = 1;
       child_meta = (uint32_t)(rc + 1) << 8;
-    } else if (a.split_mode == 0) {
+    } else if (p_split == 0) {
       const iv xk = S.Xn[g][kk];
       mid_kk = imid(xk);
       if (!(mid_kk > xk.lo && mid_kk < -xk.nhi)) {
@@ -546,15 +659,15 @@ __device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, lo
       }
     }
   }
-  if (a.split_mode != 0) {
+  if (__ballot(p_split != 0) != 0) {
     bool can = false;
-    if (alive && row_ok) {
+    if (alive && row_ok && p_split != 0) {
       const iv xr = S.Xn[g][r];
       const double m = imid(xr);
       can = m > xr.lo && m < -xr.nhi;
     }
     split_mask = (uint32_t)group_bits<G>(__ballot(can), g);
-    if (alive && !emit && kind == 0) {
+    if (alive && !emit && kind == 0 && p_split != 0) {
       if (split_mask == 0) {
         emit = true;
         tag = 0;
@@ -567,6 +680,19 @@ __device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, lo
 
   // ---- counters, once per group
   const bool leader = (r == 0) && valid;
+  if (MULTI) {
+    unsigned long long* st = a.stats_sys;
+    const uint32_t o8 = sysid * 8u;
+    sys_add(st + kProcessed, o8, 1u, leader);
+    sys_add(st + kExclEval, o8, excluded ? 1u : 0u, leader);
+    sys_add(st + kExclHs, o8, hs_empty ? 1u : 0u, leader);
+    sys_add(st + kHsSkipped, o8, (active && !run) ? 1u : 0u, leader);
+    sys_add(st + kRecontract, o8, kind == 1 ? 1u : 0u, leader);
+    sys_add(st + kBisected, o8, (kind == 2 || kind == 3) ? 1u : 0u, leader);
+    sys_add(st + kEmitU, o8, (emit && tag == 1) ? 1u : 0u, leader);
+    sys_add(st + kEmitUnd, o8, (emit && tag == 0) ? 1u : 0u, leader);
+    sys_add(a.count_sys + (size_t)((level + 1) % 3) * a.B, sysid, (unsigned)n_push, leader);
+  }
   sc.s[kProcessed] += __popcll(__ballot(leader));
   sc.s[kExclEval] += __popcll(__ballot(leader && excluded));
   sc.s[kExclHs] += __popcll(__ballot(leader && hs_empty));
@@ -586,7 +712,7 @@ __device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, lo
   unsigned long long pbase = 0, ebase = 0;
   if (lane == 0) {
     if (tot_p) pbase = atomicAdd(next_count, (unsigned long long)tot_p);
-    if (tot_e) ebase = atomicAdd(&a.ctrl->out_count, (unsigned long long)tot_e);
+    if (tot_e) ebase = atomicAdd(a.out_count, (unsigned long long)tot_e);
   }
   pbase = __shfl(pbase, 0, 64);
   ebase = __shfl(ebase, 0, 64);
@@ -599,11 +725,14 @@ __device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, lo
     if (o < (unsigned long long)a.out_cap) {
       if (row_ok) {
         const iv x = S.Xn[g][r];
-        double* dst = a.out_box + ((size_t)o * G + r) * 2;
+        double* dst = a.out_box + ((size_t)o * a.out_stride + r) * 2;
         dst[0] = x.lo;
         dst[1] = x.nhi;
       }
-      if (r == 0) a.out_tag[o] = (uint32_t)tag;
+      if (r == 0) {
+        a.out_tag[o] = (uint32_t)tag;
+        if (MULTI) a.out_sys[o] = sysid;
+      }
     }
   }
   if (n_push) {
@@ -616,7 +745,10 @@ __device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, lo
           dst[0] = x.lo;
           dst[1] = x.nhi;
         }
-        if (r == 0) a.meta[nxt][o] = child_meta;
+        if (r == 0) {
+          a.meta[nxt][o] = child_meta;
+          if (MULTI) a.sys[nxt][o] = sysid;
+        }
       }
     } else if (kind == 2) {
       for (int c = 0; c < 2; ++c) {
@@ -628,7 +760,10 @@ __device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, lo
             dst[0] = y.lo;
             dst[1] = y.nhi;
           }
-          if (r == 0) a.meta[nxt][o + c] = 0u;
+          if (r == 0) {
+            a.meta[nxt][o + c] = 0u;
+            if (MULTI) a.sys[nxt][o + c] = sysid;
+          }
         }
       }
     } else {
@@ -644,7 +779,10 @@ __device__ void step_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, lo
             dst[0] = y.lo;
             dst[1] = y.nhi;
           }
-          if (r == 0) a.meta[nxt][o + c] = 0u;
+          if (r == 0) {
+            a.meta[nxt][o + c] = 0u;
+            if (MULTI) a.sys[nxt][o + c] = sysid;
+          }
         }
       }
     }
@@ -677,14 +815,18 @@ __device__ void grid_barrier(const SolveArgs& a, unsigned long long& target) {
   __threadfence();
 }
 
-template <int G>
+template <int G, bool MULTI>
 __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
   set_fp64_round_down();
   extern __shared__ __align__(16) char smem[];
-  const SysDesc* d = reinterpret_cast<const SysDesc*>(a.blob);
-  const LTable T = stage_table(a.blob, smem);
-  Scratch<G>* S =
-      reinterpret_cast<Scratch<G>*>(smem + align16(table_lds_bytes(d->n, d->T, d->TD))) + (threadIdx.x / 64);
+  LTable T{};
+  size_t table_bytes = 0;
+  if (!MULTI) {
+    const SysDesc* d = reinterpret_cast<const SysDesc*>(a.blob);
+    T = stage_table(a.blob, smem);
+    table_bytes = align16(table_lds_bytes(d->n, d->T, d->TD));
+  }
+  Scratch<G>* S = reinterpret_cast<Scratch<G>*>(smem + table_bytes) + (threadIdx.x / 64);
   __syncthreads();
 
   constexpr int W = 64 / G;
@@ -698,15 +840,16 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
     const unsigned long long cnt =
         __hip_atomic_load(&c->count[level % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int st = __hip_atomic_load(&c->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (st != 0 || cnt == 0) break;
+    if (st != 0 || cnt == 0 || (a.max_levels > 0 && level >= a.max_levels)) break;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       if (level < a.level_cap) a.level_sizes[level] = (long long)cnt;
       c->levels = (unsigned long long)(level + 1);
       if (cnt > c->max_frontier) c->max_frontier = cnt;
     }
     // the budget is on tree nodes: it fails exactly when the tree has more
-    // than max_boxes nodes, whatever the frontier capacity
-    if (processed + cnt > (unsigned long long)a.max_boxes) {
+    // than max_boxes nodes, whatever the frontier capacity (batches check it
+    // per system inside the step)
+    if (!MULTI && processed + cnt > (unsigned long long)a.max_boxes) {
       if (blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(&c->status, 0, -2);
       break;
     }
@@ -726,7 +869,7 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
       if (lane == 0) base = atomicAdd(&c->claim[level % 3], (unsigned long long)W);
       base = __shfl(base, 0, 64);
       if (base >= cnt) break;
-      step_tile<G>(a, T, *S, (long long)base, (long long)cnt, cur, next_count, sc);
+      step_tile<G, MULTI>(a, T, *S, (long long)base, (long long)cnt, cur, level, next_count, sc);
     }
     grid_barrier(a, target);
   }
@@ -841,6 +984,66 @@ __global__ void selftest_kernel(int op, long long count, const double* x, const 
 }
 
 // ---------------------------------------------------------------------------
+// Batches: level 0 of a bucket of systems, and the per-system sorted output.
+// ---------------------------------------------------------------------------
+__global__ void batch_init_kernel(Ctrl* c, double* front0, uint32_t* meta0, uint32_t* sys0, const double* lo,
+                                  const double* hi, const int* bucket, int m, int G, const int* nsys,
+                                  unsigned long long* count_sys, int B) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < (int)(sizeof(Ctrl) / 8)) reinterpret_cast<unsigned long long*>(c)[threadIdx.x] = 0ull;
+    __syncthreads();
+    if (threadIdx.x == 0) c->count[0] = (unsigned long long)m;
+  }
+  if (t >= m) return;
+  const int s = bucket[t];
+  const int n = nsys[s];
+  for (int r = 0; r < G; ++r) {
+    front0[((size_t)t * G + r) * 2] = r < n ? lo[(size_t)s * kMaxN + r] : 0.0;
+    front0[((size_t)t * G + r) * 2 + 1] = r < n ? -hi[(size_t)s * kMaxN + r] : 0.0;
+  }
+  meta0[t] = 0u;
+  sys0[t] = (uint32_t)s;
+  count_sys[s] = 1ull;
+}
+
+// Each emitted box takes a slot in its system's segment (order within the
+// segment is fixed afterwards by the rank kernel).
+__global__ void seg_scatter_kernel(const uint32_t* out_sys, long long M, const long long* seg_off,
+                                   unsigned long long* cursor, uint32_t* order) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const uint32_t s = out_sys[i];
+  const unsigned long long k = atomicAdd(&cursor[s], 1ull);
+  order[seg_off[s] + (long long)k] = (uint32_t)i;
+}
+
+__global__ void seg_rank_kernel(const double* box, const uint32_t* tag, const uint32_t* out_sys,
+                                const uint32_t* order, const long long* seg_off, const int* nsys, long long M,
+                                double* out_lo, double* out_hi, uint8_t* out_tag) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  const uint32_t i = order[j];
+  const uint32_t s = out_sys[i];
+  const int n = nsys[s];
+  const long long a = seg_off[s], b = seg_off[s + 1];
+  const double* A = box + (size_t)i * kMaxN * 2;
+  const uint32_t ta = tag[i];
+  long long rank = 0;
+  for (long long k = a; k < b; ++k) {
+    const uint32_t e = order[k];
+    const int c = cmp_boxes(box + (size_t)e * kMaxN * 2, tag[e], A, ta, n);
+    if (c < 0 || (c == 0 && e < i)) ++rank;
+  }
+  const long long dst = a + rank;
+  for (int k = 0; k < kMaxN; ++k) {
+    out_lo[(size_t)dst * kMaxN + k] = k < n ? canon(A[2 * k]) : 0.0;
+    out_hi[(size_t)dst * kMaxN + k] = k < n ? canon(-A[2 * k + 1]) : 0.0;
+  }
+  out_tag[dst] = (uint8_t)ta;
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launch helpers (called by the runtime in api.cpp).
 // ---------------------------------------------------------------------------
 size_t scratch_bytes(int G) {
@@ -852,12 +1055,20 @@ size_t scratch_bytes(int G) {
   }
 }
 
-const void* solve_kernel_ptr(int G) {
+const void* solve_kernel_ptr(int G, bool multi) {
+  if (multi) {
+    switch (G) {
+      case 2: return reinterpret_cast<const void*>(&solve_kernel<2, true>);
+      case 4: return reinterpret_cast<const void*>(&solve_kernel<4, true>);
+      case 8: return reinterpret_cast<const void*>(&solve_kernel<8, true>);
+      default: return reinterpret_cast<const void*>(&solve_kernel<16, true>);
+    }
+  }
   switch (G) {
-    case 2: return reinterpret_cast<const void*>(&solve_kernel<2>);
-    case 4: return reinterpret_cast<const void*>(&solve_kernel<4>);
-    case 8: return reinterpret_cast<const void*>(&solve_kernel<8>);
-    default: return reinterpret_cast<const void*>(&solve_kernel<16>);
+    case 2: return reinterpret_cast<const void*>(&solve_kernel<2, false>);
+    case 4: return reinterpret_cast<const void*>(&solve_kernel<4, false>);
+    case 8: return reinterpret_cast<const void*>(&solve_kernel<8, false>);
+    default: return reinterpret_cast<const void*>(&solve_kernel<16, false>);
   }
 }
 
@@ -886,6 +1097,36 @@ hipError_t launch_selftest(hipStream_t s, int op, long long count, const double*
                            double* out) {
   const int blocks = (int)((count + 255) / 256);
   if (blocks > 0) hipLaunchKernelGGL(selftest_kernel, dim3(blocks), dim3(256), 0, s, op, count, x, y, out);
+  return hipGetLastError();
+}
+
+}  // namespace ibb
+
+namespace ibb {
+
+hipError_t launch_prep(hipStream_t s, uint64_t* blobs, const long long* blob_off, int B) {
+  if (B > 0) hipLaunchKernelGGL(prep_kernel, dim3(std::min(B, 4096)), dim3(256), 0, s, blobs, blob_off, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_init(hipStream_t s, Ctrl* c, double* front0, uint32_t* meta0, uint32_t* sys0,
+                             const double* lo, const double* hi, const int* bucket, int m, int G, const int* nsys,
+                             unsigned long long* count_sys, int B) {
+  const int blocks = std::max(1, (m + 255) / 256);
+  hipLaunchKernelGGL(batch_init_kernel, dim3(blocks), dim3(256), 0, s, c, front0, meta0, sys0, lo, hi, bucket, m,
+                     G, nsys, count_sys, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_sort(hipStream_t s, const double* box, const uint32_t* tag, const uint32_t* out_sys,
+                           long long M, const long long* seg_off, unsigned long long* cursor, uint32_t* order,
+                           const int* nsys, double* out_lo, double* out_hi, uint8_t* out_tag) {
+  const int blocks = (int)((M + 255) / 256);
+  if (blocks > 0) {
+    hipLaunchKernelGGL(seg_scatter_kernel, dim3(blocks), dim3(256), 0, s, out_sys, M, seg_off, cursor, order);
+    hipLaunchKernelGGL(seg_rank_kernel, dim3(blocks), dim3(256), 0, s, box, tag, out_sys, order, seg_off, nsys, M,
+                       out_lo, out_hi, out_tag);
+  }
   return hipGetLastError();
 }
 

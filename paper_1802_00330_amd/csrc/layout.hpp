@@ -25,7 +25,8 @@ struct SysDesc {
   int32_t eq_off_w, der_off_w, coef_w, fac_w;
   int32_t dcoef_w, dmult_w, dfac_w, total_w;
   uint32_t jnz[kMaxN];  // bit k of jnz[i]: d f_i / d x_k has at least one term
-  int32_t pad[4];
+  int32_t dco_w;        // [TD][2] enclosure (lo, -hi) of e_k * c, filled on the device
+  int32_t pad[3];
 };
 static_assert(sizeof(SysDesc) == 128, "SysDesc size");
 
@@ -44,6 +45,13 @@ struct Ctrl {
   int32_t pad[7];
 };
 
+// Per-system search parameters of a batch (ibb_params in device form).
+struct SysParams {
+  double tol, ratio, hs_max_width;
+  long long max_boxes;
+  int split_mode, max_rc;
+};
+
 struct SolveArgs {
   const uint64_t* blob;
   double* front[2];  // boxes as (lo, -hi) pairs, [cap][G][2]
@@ -59,9 +67,38 @@ struct SolveArgs {
   long long max_boxes;
   int split_mode, max_rc;
   int nblocks;
-  int pad;
+  int max_levels;           // stop after this many levels (0 = until the tree ends)
   long long timeout_ticks;  // device wall-clock ticks (100 MHz) a barrier may wait
+  double* dbg;              // diagnostics: intermediates of box 0 of level 0 (or null)
+  unsigned long long* out_count;  // emitted boxes (shared by the launches of a batch)
+  // batches of systems (null for a single system)
+  uint32_t* sys[2];               // system index of each frontier record
+  const uint64_t* blobs;          // all compiled systems
+  const long long* blob_off;      // [B] word offset of each system's blob
+  const SysParams* sp;            // [B]
+  unsigned long long* count_sys;  // [3][B] boxes of system s at level L in slot L % 3
+  unsigned long long* cum_sys;    // [2][B] tree nodes of s through level L in slot L % 2
+  int* status_sys;                // [B]
+  unsigned long long* stats_sys;  // [B][8]
+  uint32_t* out_sys;              // [out_cap] system of each emitted box
+  int B;
+  int out_stride;  // coordinates per output record (G for one system, kMaxN for batches)
 };
+
+// Layout of the diagnostic dump of one step (doubles), n = system size:
+//   J [n][n][2] (lo, hi) | F(x) [n][2] | single-precision mid J [n][n] |
+//   Y [n][n] (row = logical position) | g [n][2] | P [n][n][2] | N [n][2] |
+//   X' [n][2] | flags [4]: skipped, empty, unique, ran
+__host__ __device__ inline int dbg_off_J(int) { return 0; }
+__host__ __device__ inline int dbg_off_F(int n) { return 2 * n * n; }
+__host__ __device__ inline int dbg_off_M(int n) { return 2 * n * n + 2 * n; }
+__host__ __device__ inline int dbg_off_Y(int n) { return 3 * n * n + 2 * n; }
+__host__ __device__ inline int dbg_off_g(int n) { return 4 * n * n + 2 * n; }
+__host__ __device__ inline int dbg_off_P(int n) { return 4 * n * n + 4 * n; }
+__host__ __device__ inline int dbg_off_N(int n) { return 6 * n * n + 4 * n; }
+__host__ __device__ inline int dbg_off_X(int n) { return 6 * n * n + 6 * n; }
+__host__ __device__ inline int dbg_off_flags(int n) { return 6 * n * n + 8 * n; }
+__host__ __device__ inline int dbg_len(int n) { return 6 * n * n + 8 * n + 4; }
 
 // LDS bytes of the staged system table (kernels.hip, stage_table).
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
