@@ -136,6 +136,46 @@ int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const do
                     uint8_t* out_tag, int64_t cap, int64_t* out_off, int32_t* status,
                     ibb_stats* stats);
 
+/* ---- serving: continuous batching of solves on one device ----
+ * Requests are queued by ibb_server_submit (the system is copied).  Each call
+ * of ibb_server_step (1) admits queued requests while a device slot is free
+ * and the size bucket's frontier still has `reserve_per_solve` boxes
+ * unreserved -- admission by the device memory the request's box queue needs;
+ * (2) runs `levels_per_quantum` tree levels of every admitted solve together,
+ * new arrivals joining solves already on the device; (3) harvests the solves
+ * that ran out of boxes.  A solve keeps its boxes resident on the device until
+ * it finishes, and its result is identical to ibb_solve on it alone.
+ * Only IBB_SPLIT_WIDEST is served. */
+typedef struct {
+  int32_t max_slots;          /* solves resident on the device at once (256)    */
+  int64_t frontier_cap;       /* boxes per size bucket's frontier (2^20); grows */
+  int64_t reserve_per_solve;  /* frontier boxes reserved per admitted solve     */
+  int32_t levels_per_quantum; /* tree levels per device pass (8)                */
+  int32_t out_cap_per_solve;  /* output boxes per solve (1024)                  */
+} ibb_server_config;
+
+typedef struct ibb_server ibb_server;
+
+void ibb_server_config_default(ibb_server_config* cfg);
+/* Allocates the server's device state on the context's GPU (cfg may be NULL). */
+int ibb_server_create(ibb_ctx* ctx, const ibb_server_config* cfg, ibb_server** out);
+void ibb_server_destroy(ibb_server* server);
+/* Queues a request; returns its id (>= 0) or a negative status. */
+int64_t ibb_server_submit(ibb_server* server, const ibb_system* sys, const double* lo, const double* hi,
+                          const ibb_params* params);
+/* One scheduling round (admit, one quantum, harvest); returns the number of
+ * requests finished in this round, or a negative status. */
+int ibb_server_step(ibb_server* server);
+/* Result of a finished request (then forgotten): IBB_OK with the sorted boxes
+ * as in ibb_solve, *status the request's own status; returns 1 while the
+ * request is queued or running. */
+int ibb_server_poll(ibb_server* server, int64_t id, double* out_lo, double* out_hi, uint8_t* out_tag,
+                    int64_t cap, int64_t* n_out, int32_t* status, ibb_stats* stats);
+/* Removes a request that has not been admitted yet. */
+int ibb_server_cancel(ibb_server* server, int64_t id);
+/* Requests waiting for admission and requests on the device. */
+int ibb_server_pending(ibb_server* server, int64_t* queued, int64_t* active);
+
 /* Device workspace (bytes) that ibb_solve_async needs for a system with n
  * variables, a frontier of `frontier_cap` boxes per tree level and `out_cap`
  * output boxes. */

@@ -31,7 +31,9 @@ STATS_FIELDS = ("processed", "excluded_eval", "excluded_hs", "hs_skipped", "reco
 
 EXPORTS = ("ibb_ctx_create", "ibb_ctx_destroy", "ibb_strerror", "ibb_params_default", "ibb_solve",
            "ibb_workspace_size", "ibb_solve_async", "ibb_last_level_sizes", "ibb_last_kernel_ms",
-           "ibb_selftest_ops", "ibb_debug_step", "ibb_solve_batch")
+           "ibb_selftest_ops", "ibb_debug_step", "ibb_solve_batch", "ibb_server_config_default",
+           "ibb_server_create", "ibb_server_destroy", "ibb_server_submit", "ibb_server_step", "ibb_server_poll",
+           "ibb_server_cancel", "ibb_server_pending")
 
 
 class IbbSystem(C.Structure):
@@ -42,6 +44,11 @@ class IbbParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_boxes", C.c_int64), ("split_mode", C.c_int32),
                 ("max_recontract", C.c_int32), ("recontract_ratio", C.c_double),
                 ("hs_max_width", C.c_double)]
+
+
+class IbbServerConfig(C.Structure):
+    _fields_ = [("max_slots", C.c_int32), ("frontier_cap", C.c_int64), ("reserve_per_solve", C.c_int64),
+                ("levels_per_quantum", C.c_int32), ("out_cap_per_solve", C.c_int32)]
 
 
 class IbbStats(C.Structure):
@@ -81,6 +88,20 @@ def load_library(path: str = LIB_PATH):
     L.ibb_last_kernel_ms.restype, L.ibb_last_kernel_ms.argtypes = C.c_double, [p]
     L.ibb_solve_batch.restype = C.c_int
     L.ibb_solve_batch.argtypes = [p, i32, p, p, p, p, p, p, p, i64, p, p, p]
+    L.ibb_server_config_default.restype = None
+    L.ibb_server_config_default.argtypes = [C.POINTER(IbbServerConfig)]
+    L.ibb_server_create.restype = C.c_int
+    L.ibb_server_create.argtypes = [p, C.POINTER(IbbServerConfig), C.POINTER(C.c_void_p)]
+    L.ibb_server_destroy.restype, L.ibb_server_destroy.argtypes = None, [p]
+    L.ibb_server_submit.restype = i64
+    L.ibb_server_submit.argtypes = [p, C.POINTER(IbbSystem), p, p, C.POINTER(IbbParams)]
+    L.ibb_server_step.restype, L.ibb_server_step.argtypes = C.c_int, [p]
+    L.ibb_server_poll.restype = C.c_int
+    L.ibb_server_poll.argtypes = [p, i64, p, p, p, i64, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                  C.POINTER(IbbStats)]
+    L.ibb_server_cancel.restype, L.ibb_server_cancel.argtypes = C.c_int, [p, i64]
+    L.ibb_server_pending.restype = C.c_int
+    L.ibb_server_pending.argtypes = [p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.ibb_debug_step.restype = C.c_int
     L.ibb_debug_step.argtypes = [p, C.POINTER(IbbSystem), p, p, C.POINTER(IbbParams), p, i64]
     _lib = L
@@ -312,3 +333,73 @@ def ibb_solve_batch(ctx: Context, systems, params=None, cap: int = 1 << 16):
             sd = {f: int(getattr(stats[b], f)) for f in STATS_FIELDS}
             out.append(Result(int(status[b]), olo[a:e, :s.n].copy(), ohi[a:e, :s.n].copy(), otag[a:e].copy(), sd))
         return out
+
+
+class Server:
+    """Continuous-batching server (ibb_server_*): submit, step, poll."""
+
+    def __init__(self, ctx: Context, **cfg):
+        L = load_library()
+        c = IbbServerConfig()
+        L.ibb_server_config_default(C.byref(c))
+        for k, v in cfg.items():
+            setattr(c, k, v)
+        h = C.c_void_p()
+        st = L.ibb_server_create(ctx.handle, C.byref(c), C.byref(h))
+        if st != OK:
+            raise RuntimeError(f"ibb_server_create: {ibb_strerror(st)}")
+        self.handle = h
+        self.ctx = ctx
+        self.n = {}
+
+    def submit(self, s, params: Optional[IbbParams] = None) -> int:
+        ref = _SysRef(s)
+        lo = np.ascontiguousarray(s.lo, dtype=np.float64)
+        hi = np.ascontiguousarray(s.hi, dtype=np.float64)
+        params = params or make_params(s.tol)
+        rid = load_library().ibb_server_submit(self.handle, C.byref(ref.c), _ptr(lo), _ptr(hi), C.byref(params))
+        if rid < 0:
+            raise RuntimeError(f"ibb_server_submit: {ibb_strerror(int(rid))}")
+        self.n[rid] = s.n
+        return int(rid)
+
+    def step(self) -> int:
+        k = load_library().ibb_server_step(self.handle)
+        if k < 0:
+            raise RuntimeError(f"ibb_server_step: {ibb_strerror(k)}")
+        return int(k)
+
+    def poll(self, rid: int, cap: int = 1 << 12) -> Optional[Result]:
+        n = self.n[rid]
+        olo = np.zeros((cap, n))
+        ohi = np.zeros((cap, n))
+        otag = np.zeros(cap, dtype=np.uint8)
+        m = C.c_int64(0)
+        status = C.c_int32(0)
+        st_ = IbbStats()
+        st = load_library().ibb_server_poll(self.handle, int(rid), _ptr(olo), _ptr(ohi), _ptr(otag), int(cap),
+                                            C.byref(m), C.byref(status), C.byref(st_))
+        if st == 1:
+            return None
+        if st != OK:
+            raise RuntimeError(f"ibb_server_poll: {ibb_strerror(st)}")
+        del self.n[rid]
+        k = int(m.value) if status.value == OK else 0
+        stats = {f: int(getattr(st_, f)) for f in STATS_FIELDS}
+        return Result(int(status.value), olo[:k].copy(), ohi[:k].copy(), otag[:k].copy(), stats)
+
+    def pending(self):
+        q, a = C.c_int64(0), C.c_int64(0)
+        load_library().ibb_server_pending(self.handle, C.byref(q), C.byref(a))
+        return int(q.value), int(a.value)
+
+    def close(self):
+        if self.handle:
+            load_library().ibb_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -19,6 +21,9 @@ hipError_t launch_prep(hipStream_t s, uint64_t* blobs, const long long* blob_off
 hipError_t launch_batch_init(hipStream_t s, Ctrl* c, double* front0, uint32_t* meta0, uint32_t* sys0,
                              const double* lo, const double* hi, const int* bucket, int m, int G, const int* nsys,
                              unsigned long long* count_sys, int B);
+hipError_t launch_slot_sort(hipStream_t s, const double* box, const uint32_t* tag,
+                            const unsigned long long* slot_count, int slot, int cap, int n, double* out_lo,
+                            double* out_hi, uint8_t* out_tag);
 hipError_t launch_seg_sort(hipStream_t s, const double* box, const uint32_t* tag, const uint32_t* out_sys,
                            long long M, const long long* seg_off, unsigned long long* cursor, uint32_t* order,
                            const int* nsys, double* out_lo, double* out_hi, uint8_t* out_tag);
@@ -860,6 +865,467 @@ int ibb_selftest_ops(ibb_ctx* ctx, int32_t op, int64_t n, const double* a, const
     st = IBB_ERR_DEVICE;
   hipFree(d);
   return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving: continuous batching.  Admitted solves occupy device slots; their
+// boxes share one frontier per size bucket; each scheduling round admits
+// queued requests that fit (a free slot and frontier boxes reserved for them),
+// runs a quantum of tree levels for every bucket, and harvests the solves that
+// ran out of boxes.  A solve's result does not depend on its neighbours.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kSlotWords = 8192;  // 64 KiB of compiled table per slot
+
+struct Request {
+  int64_t id = 0;
+  Compiled comp;
+  double lo[kMaxN] = {0}, hi[kMaxN] = {0};
+  ibb_params p{};
+  int slot = -1, bucket = -1;
+  int state = 0;  // 0 queued, 1 on the device, 2 done
+  int status = IBB_OK;
+  ibb_stats stats{};
+  std::vector<double> out_lo, out_hi;
+  std::vector<uint8_t> out_tag;
+};
+
+struct Bucket {
+  int G = 0;
+  long long cap = 0;
+  Ctrl* ctrl = nullptr;
+  double* front[2] = {nullptr, nullptr};
+  uint32_t* meta[2] = {nullptr, nullptr};
+  uint32_t* sys[2] = {nullptr, nullptr};
+  void* mem = nullptr;
+  int level = 0;
+  unsigned long long count = 0;  // boxes at `level`
+  long long reserved = 0;
+  std::vector<int> slots;  // active slots
+};
+
+}  // namespace
+
+struct ibb_server {
+  ibb_ctx* ctx = nullptr;
+  ibb_server_config cfg{};
+  void* mem = nullptr;  // per-slot device state
+  uint64_t* blobs = nullptr;
+  long long* boff = nullptr;
+  SysParams* sp = nullptr;
+  int* nsys = nullptr;
+  unsigned long long *count_sys = nullptr, *cum_sys = nullptr, *stats_sys = nullptr, *slot_count = nullptr;
+  int* status_sys = nullptr;
+  double* out_box = nullptr;
+  uint32_t* out_tag = nullptr;
+  double *s_lo = nullptr, *s_hi = nullptr;
+  uint8_t* s_tag = nullptr;
+  long long* level_sizes = nullptr;
+  Bucket bk[4];
+  std::deque<Request*> queue;
+  std::map<int64_t, Request*> reqs;
+  std::vector<Request*> by_slot;
+  std::vector<int> free_slots;
+  int64_t next_id = 0;
+};
+
+namespace {
+
+int bucket_of(int G) { return G == 2 ? 0 : G == 4 ? 1 : G == 8 ? 2 : 3; }
+
+int alloc_bucket(Bucket& b, int G, long long cap) {
+  b.G = G;
+  b.cap = cap;
+  const size_t rec = sizeof(double) * 2 * G;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = round_up(o + bytes, 256);
+    return at;
+  };
+  const size_t c = take(sizeof(Ctrl)), f0 = take(rec * cap), f1 = take(rec * cap), m0 = take(4 * cap),
+               m1 = take(4 * cap), s0 = take(4 * cap), s1 = take(4 * cap);
+  if (hipMalloc(&b.mem, o) != hipSuccess) {
+    b.mem = nullptr;
+    return IBB_ERR_NO_MEMORY;
+  }
+  char* w = static_cast<char*>(b.mem);
+  b.ctrl = reinterpret_cast<Ctrl*>(w + c);
+  b.front[0] = reinterpret_cast<double*>(w + f0);
+  b.front[1] = reinterpret_cast<double*>(w + f1);
+  b.meta[0] = reinterpret_cast<uint32_t*>(w + m0);
+  b.meta[1] = reinterpret_cast<uint32_t*>(w + m1);
+  b.sys[0] = reinterpret_cast<uint32_t*>(w + s0);
+  b.sys[1] = reinterpret_cast<uint32_t*>(w + s1);
+  if (hipMemset(b.ctrl, 0, sizeof(Ctrl)) != hipSuccess) return IBB_ERR_DEVICE;
+  return IBB_OK;
+}
+
+// Moves a bucket to a larger frontier, keeping the boxes of its current level.
+int grow_bucket(Bucket& b, hipStream_t s) {
+  Bucket nb;
+  int st = alloc_bucket(nb, b.G, b.cap * 4);
+  if (st) return st;
+  const int cur = b.level & 1;
+  const size_t rec = sizeof(double) * 2 * b.G;
+  if (hipMemcpyAsync(nb.ctrl, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(nb.front[cur], b.front[cur], rec * b.count, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(nb.meta[cur], b.meta[cur], 4 * b.count, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(nb.sys[cur], b.sys[cur], 4 * b.count, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return IBB_ERR_DEVICE;
+  hipFree(b.mem);
+  nb.level = b.level;
+  nb.count = b.count;
+  nb.reserved = b.reserved;
+  nb.slots = b.slots;
+  b = nb;
+  return IBB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ibb_server_config_default(ibb_server_config* c) {
+  if (!c) return;
+  c->max_slots = 256;
+  c->frontier_cap = 1 << 20;
+  c->reserve_per_solve = 1 << 14;
+  c->levels_per_quantum = 8;
+  c->out_cap_per_solve = 1024;
+}
+
+int ibb_server_create(ibb_ctx* ctx, const ibb_server_config* cfg, ibb_server** out) {
+  if (!ctx || !out) return IBB_ERR_INVALID_ARG;
+  *out = nullptr;
+  ibb_server_config c;
+  ibb_server_config_default(&c);
+  if (cfg) c = *cfg;
+  if (c.max_slots < 1 || c.frontier_cap < 16 || c.reserve_per_solve < 1 || c.levels_per_quantum < 1 ||
+      c.out_cap_per_solve < 1 || c.reserve_per_solve > c.frontier_cap)
+    return IBB_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return IBB_ERR_DEVICE;
+  ibb_server* sv = new (std::nothrow) ibb_server();
+  if (!sv) return IBB_ERR_NO_MEMORY;
+  sv->ctx = ctx;
+  sv->cfg = c;
+  const int S = c.max_slots;
+  const long long oc = c.out_cap_per_solve;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = round_up(o + bytes, 256);
+    return at;
+  };
+  const size_t a_blobs = take(8ull * kSlotWords * S), a_boff = take(8ull * S), a_sp = take(sizeof(SysParams) * S),
+               a_n = take(4ull * S), a_cs = take(8ull * 3 * S), a_cum = take(8ull * 2 * S),
+               a_st = take(8ull * 8 * S), a_sc = take(8ull * S), a_ss = take(4ull * S),
+               a_ob = take(sizeof(double) * 2 * kMaxN * oc * S), a_ot = take(4ull * oc * S),
+               a_slo = take(sizeof(double) * kMaxN * oc), a_shi = take(sizeof(double) * kMaxN * oc),
+               a_stag = take((size_t)oc), a_lv = take(sizeof(long long) * kLevelCap);
+  if (hipMalloc(&sv->mem, o) != hipSuccess) {
+    delete sv;
+    return IBB_ERR_NO_MEMORY;
+  }
+  char* w = static_cast<char*>(sv->mem);
+  sv->blobs = reinterpret_cast<uint64_t*>(w + a_blobs);
+  sv->boff = reinterpret_cast<long long*>(w + a_boff);
+  sv->sp = reinterpret_cast<SysParams*>(w + a_sp);
+  sv->nsys = reinterpret_cast<int*>(w + a_n);
+  sv->count_sys = reinterpret_cast<unsigned long long*>(w + a_cs);
+  sv->cum_sys = reinterpret_cast<unsigned long long*>(w + a_cum);
+  sv->stats_sys = reinterpret_cast<unsigned long long*>(w + a_st);
+  sv->slot_count = reinterpret_cast<unsigned long long*>(w + a_sc);
+  sv->status_sys = reinterpret_cast<int*>(w + a_ss);
+  sv->out_box = reinterpret_cast<double*>(w + a_ob);
+  sv->out_tag = reinterpret_cast<uint32_t*>(w + a_ot);
+  sv->s_lo = reinterpret_cast<double*>(w + a_slo);
+  sv->s_hi = reinterpret_cast<double*>(w + a_shi);
+  sv->s_tag = reinterpret_cast<uint8_t*>(w + a_stag);
+  sv->level_sizes = reinterpret_cast<long long*>(w + a_lv);
+  std::vector<long long> boff((size_t)S);
+  for (int i = 0; i < S; ++i) boff[i] = (long long)i * kSlotWords;
+  int st = IBB_OK;
+  if (hipMemset(sv->mem, 0, o) != hipSuccess ||
+      hipMemcpy(sv->boff, boff.data(), 8ull * S, hipMemcpyHostToDevice) != hipSuccess)
+    st = IBB_ERR_DEVICE;
+  for (int q = 0; q < 4 && !st; ++q) st = alloc_bucket(sv->bk[q], 2 << q, c.frontier_cap);
+  if (st) {
+    ibb_server_destroy(sv);
+    return st;
+  }
+  sv->by_slot.assign((size_t)S, nullptr);
+  for (int i = S - 1; i >= 0; --i) sv->free_slots.push_back(i);
+  *out = sv;
+  return IBB_OK;
+}
+
+void ibb_server_destroy(ibb_server* sv) {
+  if (!sv) return;
+  hipSetDevice(sv->ctx->device);
+  hipStreamSynchronize(sv->ctx->stream);
+  for (auto& b : sv->bk)
+    if (b.mem) hipFree(b.mem);
+  if (sv->mem) hipFree(sv->mem);
+  for (auto& kv : sv->reqs) delete kv.second;
+  delete sv;
+}
+
+int64_t ibb_server_submit(ibb_server* sv, const ibb_system* sys, const double* lo, const double* hi,
+                          const ibb_params* params) {
+  if (!sv) return IBB_ERR_INVALID_ARG;
+  const int st = validate(sys, lo, hi, params);
+  if (st) return st;
+  if (params->split_mode != IBB_SPLIT_WIDEST) return IBB_ERR_UNSUPPORTED;
+  Request* r = new (std::nothrow) Request();
+  if (!r) return IBB_ERR_NO_MEMORY;
+  try {
+    compile(sys, r->comp);
+  } catch (...) {
+    delete r;
+    return IBB_ERR_NO_MEMORY;
+  }
+  if (r->comp.blob.size() > (size_t)kSlotWords) {
+    delete r;
+    return IBB_ERR_UNSUPPORTED;
+  }
+  r->id = sv->next_id++;
+  std::memcpy(r->lo, lo, sizeof(double) * sys->n);
+  std::memcpy(r->hi, hi, sizeof(double) * sys->n);
+  r->p = *params;
+  sv->queue.push_back(r);
+  sv->reqs[r->id] = r;
+  return r->id;
+}
+
+int ibb_server_cancel(ibb_server* sv, int64_t id) {
+  if (!sv) return IBB_ERR_INVALID_ARG;
+  auto it = sv->reqs.find(id);
+  if (it == sv->reqs.end()) return IBB_ERR_INVALID_ARG;
+  Request* r = it->second;
+  if (r->state != 0) return IBB_ERR_UNSUPPORTED;  // only queued requests can be cancelled
+  sv->queue.erase(std::find(sv->queue.begin(), sv->queue.end(), r));
+  sv->reqs.erase(it);
+  delete r;
+  return IBB_OK;
+}
+
+int ibb_server_pending(ibb_server* sv, int64_t* queued, int64_t* active) {
+  if (!sv) return IBB_ERR_INVALID_ARG;
+  if (queued) *queued = (int64_t)sv->queue.size();
+  if (active) *active = (int64_t)(sv->cfg.max_slots - (int)sv->free_slots.size());
+  return IBB_OK;
+}
+
+int ibb_server_step(ibb_server* sv) {
+  if (!sv) return IBB_ERR_INVALID_ARG;
+  ibb_ctx* ctx = sv->ctx;
+  if (hipSetDevice(ctx->device) != hipSuccess) return IBB_ERR_DEVICE;
+  hipStream_t s = ctx->stream;
+  const int S = sv->cfg.max_slots;
+  // ---- admission: a free slot and the frontier boxes the solve reserves
+  std::vector<Request*> admitted;
+  for (auto it = sv->queue.begin(); it != sv->queue.end() && !sv->free_slots.empty();) {
+    Request* r = *it;
+    Bucket& b = sv->bk[bucket_of(r->comp.G)];
+    if (b.reserved + sv->cfg.reserve_per_solve > b.cap) {
+      ++it;
+      continue;
+    }
+    it = sv->queue.erase(it);
+    r->slot = sv->free_slots.back();
+    sv->free_slots.pop_back();
+    r->bucket = bucket_of(r->comp.G);
+    r->state = 1;
+    b.reserved += sv->cfg.reserve_per_solve;
+    b.slots.push_back(r->slot);
+    sv->by_slot[r->slot] = r;
+    admitted.push_back(r);
+  }
+  for (Request* r : admitted) {
+    Bucket& b = sv->bk[r->bucket];
+    const int slot = r->slot, L = b.level, G = b.G, n = r->comp.n;
+    // table, parameters and level bookkeeping of the slot; the root box joins
+    // the bucket's frontier at its current level
+    const SysParams spv{r->p.tol, r->p.recontract_ratio, r->p.hs_max_width, r->p.max_boxes, r->p.split_mode,
+                        r->p.max_recontract};
+    unsigned long long cs[3] = {0, 0, 0};
+    cs[L % 3] = 1;
+    std::vector<double> rec((size_t)2 * G, 0.0);
+    for (int k = 0; k < n; ++k) {
+      rec[2 * k] = r->lo[k];
+      rec[2 * k + 1] = -r->hi[k];
+    }
+    const uint32_t zero = 0, sid = (uint32_t)slot;
+    const unsigned long long z8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int zi = 0;
+    const unsigned long long newc = b.count + 1;
+    bool ok = hipMemcpy(sv->blobs + (size_t)slot * kSlotWords, r->comp.blob.data(), 8 * r->comp.blob.size(),
+                        hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(sv->sp + slot, &spv, sizeof spv, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(sv->nsys + slot, &n, sizeof n, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(sv->status_sys + slot, &zi, sizeof zi, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(sv->stats_sys + (size_t)slot * 8, z8, sizeof z8, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(sv->slot_count + slot, z8, 8, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(sv->cum_sys + slot, z8, 8, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(sv->cum_sys + S + slot, z8, 8, hipMemcpyHostToDevice) == hipSuccess;
+    for (int q = 0; q < 3 && ok; ++q)
+      ok = hipMemcpy(sv->count_sys + (size_t)q * S + slot, &cs[q], 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok &&
+         hipMemcpy(b.front[L & 1] + (size_t)b.count * 2 * G, rec.data(), sizeof(double) * 2 * G,
+                   hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b.meta[L & 1] + b.count, &zero, 4, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b.sys[L & 1] + b.count, &sid, 4, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(&b.ctrl->count[L % 3], &newc, 8, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) return IBB_ERR_DEVICE;
+    b.count = newc;
+  }
+  if (!admitted.empty() && launch_prep(s, sv->blobs, sv->boff, S) != hipSuccess) return IBB_ERR_DEVICE;
+  // ---- one quantum of levels per bucket
+  bool any = false;
+  hipEventRecord(ctx->ev0, s);
+  for (int q = 0; q < 4; ++q) {
+    Bucket& b = sv->bk[q];
+    if (b.count == 0) continue;
+    // at most two children per box per level (widest split): keep the frontier
+    // within capacity for the whole quantum
+    int K = sv->cfg.levels_per_quantum;
+    while (K > 1 && (double)b.count * (double)(1ull << K) > (double)b.cap) --K;
+    while ((double)b.count * 2.0 > (double)b.cap) {
+      const int st = grow_bucket(b, s);
+      if (st) return st;
+    }
+    SolveArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.front[0] = b.front[0];
+    a.front[1] = b.front[1];
+    a.meta[0] = b.meta[0];
+    a.meta[1] = b.meta[1];
+    a.sys[0] = b.sys[0];
+    a.sys[1] = b.sys[1];
+    a.front_cap = b.cap;
+    a.out_box = sv->out_box;
+    a.out_tag = sv->out_tag;
+    a.out_stride = kMaxN;
+    a.slot_out_cap = sv->cfg.out_cap_per_solve;
+    a.slot_out_count = sv->slot_count;
+    a.ctrl = b.ctrl;
+    a.level_sizes = sv->level_sizes;
+    a.level_cap = 0;
+    a.max_boxes = 1LL << 62;
+    a.max_levels = K;
+    a.level0 = b.level;
+    a.timeout_ticks = ctx->clock_khz * 1000LL * 20;
+    a.blobs = sv->blobs;
+    a.blob_off = sv->boff;
+    a.sp = sv->sp;
+    a.count_sys = sv->count_sys;
+    a.cum_sys = sv->cum_sys;
+    a.status_sys = sv->status_sys;
+    a.stats_sys = sv->stats_sys;
+    a.B = S;
+    const void* fn = solve_kernel_ptr(b.G, true);
+    int waves = 0, blocks = 0;
+    size_t lds = 0;
+    const int st = persistent_geometry(ctx, fn, 0, b.G, &waves, &lds, &blocks);
+    if (st) return st;
+    a.nblocks = blocks;
+    void* args[] = {&a};
+    if (hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(64 * waves), args, (unsigned)lds, s) != hipSuccess)
+      return IBB_ERR_DEVICE;
+    any = true;
+  }
+  hipEventRecord(ctx->ev1, s);
+  ctx->timed_pending = any;
+  // ---- bring back the control blocks and the per-slot counters
+  Ctrl ctrls[4];
+  std::vector<unsigned long long> cs((size_t)3 * S), st8((size_t)8 * S);
+  std::vector<int> sst((size_t)S);
+  if (hipMemcpyAsync(&ctrls[0], sv->bk[0].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&ctrls[1], sv->bk[1].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&ctrls[2], sv->bk[2].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&ctrls[3], sv->bk[3].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(cs.data(), sv->count_sys, 8ull * 3 * S, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(st8.data(), sv->stats_sys, 8ull * 8 * S, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(sst.data(), sv->status_sys, 4ull * S, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return IBB_ERR_DEVICE;
+  for (int q = 0; q < 4; ++q) {
+    Bucket& b = sv->bk[q];
+    if (b.count == 0) continue;
+    if (ctrls[q].status != 0) return ctrls[q].status;
+    if ((int)ctrls[q].levels > b.level) b.level = (int)ctrls[q].levels;
+    b.count = ctrls[q].count[b.level % 3];
+  }
+  // ---- harvest the solves without boxes left
+  int finished = 0;
+  std::vector<unsigned long long> emitted((size_t)S);
+  if (hipMemcpy(emitted.data(), sv->slot_count, 8ull * S, hipMemcpyDeviceToHost) != hipSuccess) return IBB_ERR_DEVICE;
+  for (int q = 0; q < 4; ++q) {
+    Bucket& b = sv->bk[q];
+    for (size_t i = 0; i < b.slots.size();) {
+      const int slot = b.slots[i];
+      if (cs[(size_t)(b.level % 3) * S + slot] != 0) {
+        ++i;
+        continue;
+      }
+      Request* r = sv->by_slot[slot];
+      const int n = r->comp.n;
+      r->status = sst[slot];
+      int64_t* f = &r->stats.processed;
+      for (int k = 0; k < 8; ++k) f[k] = (int64_t)st8[(size_t)slot * 8 + k];
+      const long long m = (long long)emitted[slot];
+      if (r->status == IBB_OK && m > sv->cfg.out_cap_per_solve) r->status = IBB_ERR_OUTPUT_CAPACITY;
+      if (r->status == IBB_OK && m > 0) {
+        r->out_lo.resize((size_t)m * n);
+        r->out_hi.resize((size_t)m * n);
+        r->out_tag.resize((size_t)m);
+        if (launch_slot_sort(s, sv->out_box, sv->out_tag, sv->slot_count, slot, sv->cfg.out_cap_per_solve, n,
+                             sv->s_lo, sv->s_hi, sv->s_tag) != hipSuccess ||
+            hipMemcpyAsync(r->out_lo.data(), sv->s_lo, sizeof(double) * m * n, hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(r->out_hi.data(), sv->s_hi, sizeof(double) * m * n, hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(r->out_tag.data(), sv->s_tag, (size_t)m, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+          return IBB_ERR_DEVICE;
+      }
+      r->state = 2;
+      sv->by_slot[slot] = nullptr;
+      sv->free_slots.push_back(slot);
+      b.reserved -= sv->cfg.reserve_per_solve;
+      b.slots[i] = b.slots.back();
+      b.slots.pop_back();
+      ++finished;
+    }
+  }
+  return finished;
+}
+
+int ibb_server_poll(ibb_server* sv, int64_t id, double* out_lo, double* out_hi, uint8_t* out_tag, int64_t cap,
+                    int64_t* n_out, int32_t* status, ibb_stats* stats) {
+  if (!sv || !n_out || !status) return IBB_ERR_INVALID_ARG;
+  auto it = sv->reqs.find(id);
+  if (it == sv->reqs.end()) return IBB_ERR_INVALID_ARG;
+  Request* r = it->second;
+  if (r->state != 2) return 1;  // not finished yet
+  const int64_t m = (int64_t)r->out_tag.size();
+  *n_out = m;
+  *status = r->status;
+  if (stats) *stats = r->stats;
+  if (m > cap) return IBB_ERR_OUTPUT_CAPACITY;
+  if (m) {
+    std::memcpy(out_lo, r->out_lo.data(), sizeof(double) * r->out_lo.size());
+    std::memcpy(out_hi, r->out_hi.data(), sizeof(double) * r->out_hi.size());
+    std::memcpy(out_tag, r->out_tag.data(), (size_t)m);
+  }
+  sv->reqs.erase(it);
+  delete r;
+  return IBB_OK;
 }
 
 }  // extern "C"

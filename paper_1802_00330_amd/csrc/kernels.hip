@@ -712,7 +712,7 @@ __device__ void step_tile(const SolveArgs& a, const LTable& Tl, Scratch<G>& S, l
   unsigned long long pbase = 0, ebase = 0;
   if (lane == 0) {
     if (tot_p) pbase = atomicAdd(next_count, (unsigned long long)tot_p);
-    if (tot_e) ebase = atomicAdd(a.out_count, (unsigned long long)tot_e);
+    if (tot_e && !(MULTI && a.slot_out_cap > 0)) ebase = atomicAdd(a.out_count, (unsigned long long)tot_e);
   }
   pbase = __shfl(pbase, 0, 64);
   ebase = __shfl(ebase, 0, 64);
@@ -720,7 +720,25 @@ __device__ void step_tile(const SolveArgs& a, const LTable& Tl, Scratch<G>& S, l
   const unsigned ge = __shfl(incl_e - my_emit, g * G, 64);
 
   const int nxt = cur ^ 1;
-  if (emit) {
+  unsigned long long slot_o = 0;
+  if (MULTI && a.slot_out_cap > 0) {
+    // per-system output regions (serving): one record per emitted box
+    if (emit && r == 0) slot_o = atomicAdd(&a.slot_out_count[sysid], 1ull);
+    slot_o = __shfl(slot_o, g * G, 64);
+  }
+  if (emit && MULTI && a.slot_out_cap > 0) {
+    const unsigned long long o = slot_o;
+    if (o < (unsigned long long)a.slot_out_cap) {
+      const size_t rec = (size_t)sysid * a.slot_out_cap + o;
+      if (row_ok) {
+        const iv x = S.Xn[g][r];
+        double* dst = a.out_box + (rec * a.out_stride + r) * 2;
+        dst[0] = x.lo;
+        dst[1] = x.nhi;
+      }
+      if (r == 0) a.out_tag[rec] = (uint32_t)tag;
+    }
+  } else if (emit) {
     const unsigned long long o = ebase + ge;
     if (o < (unsigned long long)a.out_cap) {
       if (row_ok) {
@@ -836,11 +854,11 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
   unsigned long long processed = 0, target = 0;
   const int lane = __lane_id();
   Ctrl* c = a.ctrl;
-  for (int level = 0;; ++level) {
+  for (int level = a.level0;; ++level) {
     const unsigned long long cnt =
         __hip_atomic_load(&c->count[level % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int st = __hip_atomic_load(&c->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (st != 0 || cnt == 0 || (a.max_levels > 0 && level >= a.max_levels)) break;
+    if (st != 0 || cnt == 0 || (a.max_levels > 0 && level >= a.level0 + a.max_levels)) break;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       if (level < a.level_cap) a.level_sizes[level] = (long long)cnt;
       c->levels = (unsigned long long)(level + 1);
@@ -1043,6 +1061,27 @@ __global__ void seg_rank_kernel(const double* box, const uint32_t* tag, const ui
   out_tag[dst] = (uint8_t)ta;
 }
 
+// Sorted output of one system's region (serving).
+__global__ void slot_sort_kernel(const double* box, const uint32_t* tag, const unsigned long long* slot_count,
+                                 int slot, int cap, int n, double* out_lo, double* out_hi, uint8_t* out_tag) {
+  const long long m = (long long)min((unsigned long long)cap, slot_count[slot]);
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const size_t base = (size_t)slot * cap;
+  const double* A = box + (base + i) * kMaxN * 2;
+  const uint32_t ta = tag[base + i];
+  long long rank = 0;
+  for (long long j = 0; j < m; ++j) {
+    const int c = cmp_boxes(box + (base + j) * kMaxN * 2, tag[base + j], A, ta, n);
+    if (c < 0 || (c == 0 && j < i)) ++rank;
+  }
+  for (int k = 0; k < n; ++k) {
+    out_lo[(size_t)rank * n + k] = canon(A[2 * k]);
+    out_hi[(size_t)rank * n + k] = canon(-A[2 * k + 1]);
+  }
+  out_tag[rank] = (uint8_t)ta;
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launch helpers (called by the runtime in api.cpp).
 // ---------------------------------------------------------------------------
@@ -1127,6 +1166,18 @@ hipError_t launch_seg_sort(hipStream_t s, const double* box, const uint32_t* tag
     hipLaunchKernelGGL(seg_rank_kernel, dim3(blocks), dim3(256), 0, s, box, tag, out_sys, order, seg_off, nsys, M,
                        out_lo, out_hi, out_tag);
   }
+  return hipGetLastError();
+}
+
+}  // namespace ibb
+
+namespace ibb {
+
+hipError_t launch_slot_sort(hipStream_t s, const double* box, const uint32_t* tag,
+                            const unsigned long long* slot_count, int slot, int cap, int n, double* out_lo,
+                            double* out_hi, uint8_t* out_tag) {
+  hipLaunchKernelGGL(slot_sort_kernel, dim3((cap + 255) / 256), dim3(256), 0, s, box, tag, slot_count, slot, cap,
+                     n, out_lo, out_hi, out_tag);
   return hipGetLastError();
 }
 

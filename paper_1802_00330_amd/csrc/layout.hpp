@@ -83,6 +83,9 @@ struct SolveArgs {
   uint32_t* out_sys;              // [out_cap] system of each emitted box
   int B;
   int out_stride;  // coordinates per output record (G for one system, kMaxN for batches)
+  int level0;      // index of the first level of this launch (continuing searches)
+  int slot_out_cap;  // > 0: each system emits into its own region of this many boxes
+  unsigned long long* slot_out_count;  // [B] boxes emitted per system (regions)
 };
 
 // Layout of the diagnostic dump of one step (doubles), n = system size:
