@@ -52,6 +52,74 @@ def flop_model(s):
     return f_eval, f_hs, f32
 
 
+def batched_leg(ctx, P, W, count, budget, plain_sample, log):
+    """4096 planted systems (n 2..12, degree 2..4) in one batched pass vs the
+    plain per-system solver on a sample of the same systems."""
+    import numpy as np
+    t = time.perf_counter()
+    systems = W.batch_planted(0, count=count)
+    log(f"[bench] batch: generated {count} systems in {time.perf_counter() - t:.1f} s")
+    params = [P.make_params(s.tol, max_boxes=budget) for s in systems]
+    P.ibb_solve_batch(ctx, systems[:64], params[:64])  # warm-up
+    t = time.perf_counter()
+    res = P.ibb_solve_batch(ctx, systems, params)
+    dt = time.perf_counter() - t
+    kms = P.ibb_last_kernel_ms(ctx)
+    nodes = sum(r.stats["processed"] for r in res)
+    done = sum(1 for r in res if r.status == 0)
+    # plain solver, one system per call, on the first systems of the batch
+    t = time.perf_counter()
+    pn = 0
+    for s, p in zip(systems[:plain_sample], params[:plain_sample]):
+        r = P.ibb_solve(ctx, s, p)
+        pn += r.stats["processed"]
+    pdt = time.perf_counter() - t
+    bn = sum(r.stats["processed"] for r in res[:plain_sample])
+    return {"systems": count, "budget_nodes_per_system": budget, "completed": done,
+            "over_budget": count - done, "tree_nodes": nodes, "seconds": dt, "kernel_ms": kms,
+            "boxes_per_s": nodes / dt, "solves_per_s": count / dt,
+            "plain": {"systems": plain_sample, "tree_nodes": pn, "seconds": pdt, "boxes_per_s": pn / pdt,
+                      "solves_per_s": plain_sample / pdt},
+            "batched_vs_plain_boxes_per_s": (nodes / dt) / (pn / pdt) if pn else None,
+            "same_nodes_as_plain": bool(pn == bn)}
+
+
+def served_leg(ctx, P, W, rate, duration, log):
+    """Poisson arrivals (banded n=12 and products of quadratics, tol 1e-8)
+    through the continuous-batching server; latency = arrival to result."""
+    import numpy as np
+    stream = W.served_stream(0, rate=rate, duration=duration)
+    log(f"[bench] served: {len(stream)} requests over {duration} s at {rate}/s")
+    srv = P.Server(ctx, max_slots=1024, frontier_cap=1 << 21, reserve_per_solve=1 << 11, levels_per_quantum=8)
+    t0 = time.perf_counter()
+    i = 0
+    live = {}
+    lat = []
+    nodes = 0
+    while i < len(stream) or live:
+        now = time.perf_counter() - t0
+        while i < len(stream) and stream[i][0] <= now:
+            live[srv.submit(stream[i][1])] = stream[i][0]
+            i += 1
+        if not live:
+            time.sleep(max(0.0, stream[i][0] - now))
+            continue
+        srv.step()
+        now = time.perf_counter() - t0
+        for rid in list(live):
+            r = srv.poll(rid)
+            if r is not None:
+                lat.append(now - live.pop(rid))
+                nodes += r.stats["processed"]
+    total = time.perf_counter() - t0
+    srv.close()
+    lat = np.array(lat)
+    return {"requests": len(stream), "offered_rate_per_s": rate, "seconds": total,
+            "solves_per_s": len(stream) / total, "boxes_per_s": nodes / total,
+            "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
+            "latency_ms_p99": float(np.percentile(lat, 99) * 1e3)}
+
+
 def cpu_baseline(s, sample_nodes):
     import oracle
     t = time.perf_counter()
@@ -70,6 +138,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=300_000, help="tree nodes the oracle times (0 = skip)")
+    ap.add_argument("--batch", type=int, default=4096, help="systems in the batched leg (0 = skip)")
+    ap.add_argument("--batch-budget", type=int, default=100_000, help="tree nodes per system in the batch")
+    ap.add_argument("--plain-sample", type=int, default=64)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=1.0, help="arrival window of the served leg (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the search has no multi-GPU path in this build "
@@ -156,7 +229,7 @@ def main():
     flops = excl * f_eval + contracted * f_hs + contracted * f32 / 2.0  # FP32 at twice the FP64 rate
     kmean = float(np.mean(kms)) / 1e3
     achieved = flops / kmean
-    G = 8
+    G = 2 if s.n <= 2 else 4 if s.n <= 4 else 8 if s.n <= 8 else 16
     bytes_alg = nodes * (16 * G + 4) + (int(inf[7]) * 2 + int(inf[6])) * (16 * G + 4)
 
     out = {
@@ -185,6 +258,12 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK, "traffic": None,
                      "algorithmic_bytes_per_launch": bytes_alg},
     }
+    if args.batch > 0:
+        out["batched"] = batched_leg(ctx, P, W, args.batch, args.batch_budget, args.plain_sample, log)
+        log(f"[bench] batched: {out['batched']}")
+    if args.serve_seconds > 0:
+        out["served"] = served_leg(ctx, P, W, args.serve_rate, args.serve_seconds, log)
+        log(f"[bench] served: {out['served']}")
     if args.cpu_sample > 0:
         log(f"[bench] timing the oracle on {args.cpu_sample} nodes")
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_sample)
