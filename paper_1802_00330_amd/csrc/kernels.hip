@@ -83,7 +83,7 @@ struct LTable {
 };
 
 // All threads of the block cooperate; requires the FP64 round-down mode.
-__device__ LTable stage_table(const uint64_t* blob, char* lds) {
+__device__ __forceinline__ LTable stage_table(const uint64_t* blob, char* lds) {
   const SysDesc* d = reinterpret_cast<const SysDesc*>(blob);
   const int n = d->n, T = d->T, TD = d->TD;
   char* p = lds;
@@ -222,7 +222,7 @@ enum : int { kProcessed = 0, kExclEval, kExclHs, kHsSkipped, kRecontract, kBisec
 // with X_i and the hull of the pieces (eq 21-22).  Returns false when the
 // intersection is empty.  `inside` reports Y strictly inside X_i with Q one
 // bounded interval (the uniqueness condition of Alg. 3).
-__device__ __noinline__ bool gs_component(iv N, iv P, double xc, iv Xi, iv& Xn, bool& inside) {
+__device__ __forceinline__ bool gs_component(iv N, iv P, double xc, iv Xi, iv& Xn, bool& inside) {
   const double na = N.lo, nb = -N.nhi;
   const double pc = P.lo, pd = -P.nhi;
   const double INF = __builtin_huge_val();
@@ -296,7 +296,7 @@ __device__ __forceinline__ void sys_add(unsigned long long* arr, uint32_t sysid,
 }
 
 template <int G, bool MULTI>
-__device__ void step_tile(const SolveArgs& a, const LTable& Tl, Scratch<G>& S, long long base,
+__device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, Scratch<G>& S, long long base,
                           long long cnt, int cur, int level, unsigned long long* next_count,
                           StepCounters& sc) {
   const int lane = __lane_id();
@@ -503,13 +503,11 @@ __device__ void step_tile(const SolveArgs& a, const LTable& Tl, Scratch<G>& S, l
 
     // H6, H7: this lane holds row `pos` of Y.
     //   g_pos = sum_m Y[pos][m] F_m(x),  P[pos][j] = sum_m Y[pos][m] J[m][j],
-    // m ascending from the first term; exactly-zero terms are omitted.
-    iv P[G];
+    // m ascending from the first term; exactly-zero terms are omitted.  P is
+    // formed column by column; once every lane has read column j of J, the
+    // column is overwritten by column j of P (row = logical position).
     iv gv{0.0, 0.0};
-#pragma unroll
-    for (int j = 0; j < G; ++j) P[j] = iv{0.0, 0.0};
     if (run && row_ok) {
-      uint32_t have = 0;
       bool hg = false;
       for (int m = 0; m < n; ++m) {
         float ym = 0.0f;
@@ -517,57 +515,50 @@ __device__ void step_tile(const SolveArgs& a, const LTable& Tl, Scratch<G>& S, l
         for (int c = 0; c < G; ++c)
           if (c == m) ym = z[c];
         const double y = (double)ym;
-        if (y != 0.0) {
-          const iv fm = S.Fc[g][m];
-          if (!is_zero(fm)) {
-            const iv t = pmul(y, fm);
-            gv = hg ? iadd(gv, t) : t;
-            hg = true;
-          }
-          const uint32_t nz = T.jnz[m];
-#pragma unroll
-          for (int j = 0; j < G; ++j) {
-            if (j < n && ((nz >> j) & 1u)) {
-              const iv t = pmul(y, S.J[g][m][j]);
-              P[j] = ((have >> j) & 1u) ? iadd(P[j], t) : t;
-              have |= 1u << j;
-            }
-          }
+        const iv fm = S.Fc[g][m];
+        if (y != 0.0 && !is_zero(fm)) {
+          const iv t = pmul(y, fm);
+          gv = hg ? iadd(gv, t) : t;
+          hg = true;
         }
       }
     }
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      iv pj{0.0, 0.0};
+      if (run && row_ok && j < n) {
+        bool have = false;
+#pragma unroll
+        for (int m = 0; m < G; ++m) {
+          if (m < n && ((T.jnz[m] >> j) & 1u) && z[m] != 0.0f) {
+            const iv t = pmul((double)z[m], S.J[g][m][j]);
+            pj = have ? iadd(pj, t) : t;
+            have = true;
+          }
+        }
+      }
+      wave_lds_sync();
+      if (run && row_ok && j < n) S.J[g][pos][j] = pj;
+    }
+    wave_lds_sync();
     if (dbg && run && row_ok) {
       dbg[dbg_off_g(n) + 2 * pos] = gv.lo;
       dbg[dbg_off_g(n) + 2 * pos + 1] = -gv.nhi;
-#pragma unroll
-      for (int j = 0; j < G; ++j) {
-        if (j < n) {
-          dbg[dbg_off_P(n) + (pos * n + j) * 2] = P[j].lo;
-          dbg[dbg_off_P(n) + (pos * n + j) * 2 + 1] = -P[j].nhi;
-        }
+      for (int j = 0; j < n; ++j) {
+        dbg[dbg_off_P(n) + (pos * n + j) * 2] = S.J[g][pos][j].lo;
+        dbg[dbg_off_P(n) + (pos * n + j) * 2 + 1] = -S.J[g][pos][j].nhi;
       }
     }
     // S_U = sum_{j > pos} P[pos][j] (X_j - x_j), j ascending
     iv SU{0.0, 0.0};
     bool hasU = false;
     if (run && row_ok) {
-#pragma unroll
-      for (int j = 0; j < G; ++j) {
-        if (j < n && j > pos) {
-          const iv t = imul(P[j], S.D[g][j]);
-          SU = hasU ? iadd(SU, t) : t;
-          hasU = true;
-        }
+      for (int j = pos + 1; j < n; ++j) {
+        const iv t = imul(S.J[g][pos][j], S.D[g][j]);
+        SU = hasU ? iadd(SU, t) : t;
+        hasU = true;
       }
     }
-    // P rows replace J in LDS (row = logical position) for the sweep
-    wave_lds_sync();
-    if (run && row_ok) {
-#pragma unroll
-      for (int j = 0; j < G; ++j)
-        if (j < n) S.J[g][pos][j] = P[j];
-    }
-    wave_lds_sync();
 
     // H9: Gauss-Seidel sweep (eq 21-22).  The bracket
     //   g_i + sum_{j<i} P_ij (X'_j - x_j) + sum_{j>i} P_ij (X_j - x_j)
@@ -813,7 +804,7 @@ __device__ void step_tile(const SolveArgs& a, const LTable& Tl, Scratch<G>& S, l
 // the 100 MHz device clock the barrier records IBB_ERR_TIMEOUT and returns, and
 // every later wait returns as soon as it sees a non-zero status.
 // ---------------------------------------------------------------------------
-__device__ void grid_barrier(const SolveArgs& a, unsigned long long& target) {
+__device__ __forceinline__ void grid_barrier(const SolveArgs& a, unsigned long long& target) {
   __threadfence();
   __syncthreads();
   target += (unsigned long long)a.nblocks;
