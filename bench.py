@@ -120,6 +120,28 @@ def served_leg(ctx, P, W, rate, duration, log):
             "latency_ms_p99": float(np.percentile(lat, 99) * 1e3)}
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1802_00330_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(nodes):
+    """HBM bytes per launch of the search kernel from the committed rocprofv3
+    counter summary, when it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "solve_kernel_dense6_traffic.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("kernel_source") != kernel_source_hash() or t.get("tree_nodes") != nodes:
+        return None
+    return t["hbm_bytes_per_launch"]
+
+
 def cpu_baseline(s, sample_nodes):
     import oracle
     t = time.perf_counter()
@@ -143,6 +165,8 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=64)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="arrival window of the served leg (0 = skip)")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="MiB copied by a plain device copy before the solves (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the search has no multi-GPU path in this build "
@@ -158,6 +182,13 @@ def main():
     assert torch.cuda.is_available(), "no GPU visible"
     dev = torch.device("cuda:0")
     ctx = P.Context(0)
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {args.copy_probe} MiB read, {args.copy_probe} MiB written")
+        del src, dst
     s = W.dense_planted(args.seed)
     params = P.make_params(s.tol)
     stream = torch.cuda.current_stream(dev)
@@ -253,9 +284,10 @@ def main():
         "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
         "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
         "kernel_ms_mean": kmean * 1e3,
+        "kernel_source": kernel_source_hash(),
         "bit_exact_vs_oracle": exact,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK, "traffic": measured_traffic(nodes),
                      "algorithmic_bytes_per_launch": bytes_alg},
     }
     if args.batch > 0:
