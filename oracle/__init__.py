@@ -57,6 +57,8 @@ def lib():
         L.oracle_eval_J.restype, L.oracle_eval_J.argtypes = None, [C.c_int, p, p, p, p, p, p, p]
         L.oracle_fp32_inverse.restype, L.oracle_fp32_inverse.argtypes = C.c_int, [C.c_int, p, p]
         L.oracle_hs.restype, L.oracle_hs.argtypes = C.c_int, [C.c_int, p, p, p, p, p, p, p, p]
+        L.oracle_set_chain.restype, L.oracle_set_chain.argtypes = None, [p, i64]
+        L.oracle_chain_len.restype, L.oracle_chain_len.argtypes = i64, []
         L.oracle_hs_trace.restype = C.c_int
         L.oracle_hs_trace.argtypes = [C.c_int, p, p, p, p, p, p]
         L.oracle_solve.restype = C.c_int
@@ -151,6 +153,20 @@ def hs_trace(s, lo, hi):
     tr = np.zeros(6 * s.n * s.n + 8 * s.n + 4)
     st = lib().oracle_hs_trace(s.n, _ptr(to), _ptr(ex), _ptr(co), _ptr(lo), _ptr(hi), _ptr(tr))
     return st, tr
+
+
+def proof_chains(s, cap=4096, **kw):
+    """Boxes stepped while proven (or when proven) during a solve: list of
+    (lo, hi, lo', hi')."""
+    buf = np.zeros(cap * 4 * s.n)
+    lib().oracle_set_chain(_ptr(buf), cap)
+    try:
+        solve(s, **kw)
+        m = int(lib().oracle_chain_len())
+    finally:
+        lib().oracle_set_chain(None, 0)
+    d = buf[: m * 4 * s.n].reshape(m, 4, s.n)
+    return [(d[i, 0], d[i, 1], d[i, 2], d[i, 3]) for i in range(m)]
 
 
 @dataclass

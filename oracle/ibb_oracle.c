@@ -728,6 +728,32 @@ static int valid_input(int n, const int32_t* term_off, const uint8_t* expo, cons
   return 1;
 }
 
+/* Optional record of the proof chains of a solve (test infrastructure): for
+ * every stepped box that is proven or becomes proven, its box and the
+ * contracted box, 4n doubles (lo, hi, lo', hi').  Set by oracle_set_chain. */
+static double* g_chain = NULL;
+static int64_t g_chain_cap = 0, g_chain_len = 0;
+
+void oracle_set_chain(double* buf, int64_t cap) {
+  g_chain = buf;
+  g_chain_cap = cap;
+  g_chain_len = 0;
+}
+
+int64_t oracle_chain_len(void) { return g_chain_len; }
+
+static void chain_record(const ival* X, const ival* Xn, int n) {
+  if (!g_chain || g_chain_len >= g_chain_cap) return;
+  double* d = g_chain + (size_t)g_chain_len * 4 * n;
+  for (int k = 0; k < n; ++k) {
+    d[k] = X[k].lo;
+    d[n + k] = X[k].hi;
+    d[2 * n + k] = Xn[k].lo;
+    d[3 * n + k] = Xn[k].hi;
+  }
+  g_chain_len++;
+}
+
 /* Solve: returns a status; on success the sorted boxes and tags.
  * order: 0 = last in first out, 1 = first in first out, 2 = random (seeded).
  * stats_out: 8 int64 counters (see ostats). */
@@ -806,6 +832,7 @@ int oracle_solve(int n, const int32_t* term_off, const uint8_t* expo, const doub
       u = 0;
     }
     int proven = b.proven || u;
+    if (proven) chain_record(b.X, Xn, n);
     double wn = box_width(Xn, n);
 
     if (wn <= p.tol) {

@@ -399,11 +399,11 @@ BatchLayout batch_layout(int B, size_t blob_words, long long fcap, long long oca
   L.nsys = take(sizeof(int) * B);
   L.lo = take(sizeof(double) * kMaxN * B);
   L.hi = take(sizeof(double) * kMaxN * B);
-  L.count_sys = take(sizeof(unsigned long long) * 3 * B);
+  L.bucket = take(sizeof(int) * B);
+  L.count_sys = take(sizeof(unsigned long long) * 3 * B);  // zeroed together: count_sys .. stats_sys
   L.cum_sys = take(sizeof(unsigned long long) * 2 * B);
   L.status_sys = take(sizeof(int) * B);
   L.stats_sys = take(sizeof(unsigned long long) * 8 * B);
-  L.bucket = take(sizeof(int) * B);
   L.ctrl = take(sizeof(Ctrl) * 4);
   L.level = take(sizeof(long long) * kLevelCap);
   L.front0 = take(sizeof(double) * 2 * kMaxN * (size_t)fcap);
@@ -918,6 +918,7 @@ struct ibb_server {
   SysParams* sp = nullptr;
   int* nsys = nullptr;
   unsigned long long *count_sys = nullptr, *cum_sys = nullptr, *stats_sys = nullptr, *slot_count = nullptr;
+  unsigned long long* pending = nullptr;  // boxes of each slot still in a frontier
   int* status_sys = nullptr;
   double* out_box = nullptr;
   uint32_t* out_tag = nullptr;
@@ -1026,7 +1027,7 @@ int ibb_server_create(ibb_ctx* ctx, const ibb_server_config* cfg, ibb_server** o
                a_st = take(8ull * 8 * S), a_sc = take(8ull * S), a_ss = take(4ull * S),
                a_ob = take(sizeof(double) * 2 * kMaxN * oc * S), a_ot = take(4ull * oc * S),
                a_slo = take(sizeof(double) * kMaxN * oc), a_shi = take(sizeof(double) * kMaxN * oc),
-               a_stag = take((size_t)oc), a_lv = take(sizeof(long long) * kLevelCap);
+               a_stag = take((size_t)oc), a_lv = take(sizeof(long long) * kLevelCap), a_pd = take(8ull * S);
   if (hipMalloc(&sv->mem, o) != hipSuccess) {
     delete sv;
     return IBB_ERR_NO_MEMORY;
@@ -1047,6 +1048,7 @@ int ibb_server_create(ibb_ctx* ctx, const ibb_server_config* cfg, ibb_server** o
   sv->s_hi = reinterpret_cast<double*>(w + a_shi);
   sv->s_tag = reinterpret_cast<uint8_t*>(w + a_stag);
   sv->level_sizes = reinterpret_cast<long long*>(w + a_lv);
+  sv->pending = reinterpret_cast<unsigned long long*>(w + a_pd);
   std::vector<long long> boff((size_t)S);
   for (int i = 0; i < S; ++i) boff[i] = (long long)i * kSlotWords;
   int st = IBB_OK;
@@ -1172,7 +1174,8 @@ int ibb_server_step(ibb_server* sv) {
               hipMemcpy(sv->stats_sys + (size_t)slot * 8, z8, sizeof z8, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(sv->slot_count + slot, z8, 8, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(sv->cum_sys + slot, z8, 8, hipMemcpyHostToDevice) == hipSuccess &&
-              hipMemcpy(sv->cum_sys + S + slot, z8, 8, hipMemcpyHostToDevice) == hipSuccess;
+              hipMemcpy(sv->cum_sys + S + slot, z8, 8, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(sv->pending + slot, &cs[L % 3], 8, hipMemcpyHostToDevice) == hipSuccess;
     for (int q = 0; q < 3 && ok; ++q)
       ok = hipMemcpy(sv->count_sys + (size_t)q * S + slot, &cs[q], 8, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok &&
@@ -1199,6 +1202,9 @@ int ibb_server_step(ibb_server* sv) {
       const int st = grow_bucket(b, s);
       if (st) return st;
     }
+    const unsigned long long zero_bar = 0;
+    if (hipMemcpy(&b.ctrl->bar, &zero_bar, sizeof zero_bar, hipMemcpyHostToDevice) != hipSuccess)
+      return IBB_ERR_DEVICE;
     SolveArgs a;
     std::memset(&a, 0, sizeof a);
     a.front[0] = b.front[0];
@@ -1227,6 +1233,7 @@ int ibb_server_step(ibb_server* sv) {
     a.cum_sys = sv->cum_sys;
     a.status_sys = sv->status_sys;
     a.stats_sys = sv->stats_sys;
+    a.pending_sys = sv->pending;
     a.B = S;
     const void* fn = solve_kernel_ptr(b.G, true);
     int waves = 0, blocks = 0;
@@ -1243,13 +1250,13 @@ int ibb_server_step(ibb_server* sv) {
   ctx->timed_pending = any;
   // ---- bring back the control blocks and the per-slot counters
   Ctrl ctrls[4];
-  std::vector<unsigned long long> cs((size_t)3 * S), st8((size_t)8 * S);
+  std::vector<unsigned long long> cs((size_t)S), st8((size_t)8 * S);
   std::vector<int> sst((size_t)S);
   if (hipMemcpyAsync(&ctrls[0], sv->bk[0].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(&ctrls[1], sv->bk[1].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(&ctrls[2], sv->bk[2].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(&ctrls[3], sv->bk[3].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(cs.data(), sv->count_sys, 8ull * 3 * S, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(cs.data(), sv->pending, 8ull * S, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(st8.data(), sv->stats_sys, 8ull * 8 * S, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(sst.data(), sv->status_sys, 4ull * S, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
@@ -1269,7 +1276,7 @@ int ibb_server_step(ibb_server* sv) {
     Bucket& b = sv->bk[q];
     for (size_t i = 0; i < b.slots.size();) {
       const int slot = b.slots[i];
-      if (cs[(size_t)(b.level % 3) * S + slot] != 0) {
+      if (cs[(size_t)slot] != 0) {
         ++i;
         continue;
       }

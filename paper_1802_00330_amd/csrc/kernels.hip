@@ -289,9 +289,9 @@ __device__ __forceinline__ void sys_add(unsigned long long* arr, uint32_t sysid,
   const bool same = __ballot(leader && sysid != s0) == 0;
   if (same) {
     const unsigned tot = __shfl(wave_inclusive_sum(leader ? v : 0u), 63, 64);
-    if (__lane_id() == 0 && tot) atomicAdd(&arr[s0], (unsigned long long)tot);
+    if (__lane_id() == 0 && tot) atomicAdd(&arr[s0], (unsigned long long)(long long)(int)tot);
   } else if (leader && v) {
-    atomicAdd(&arr[sysid], (unsigned long long)v);
+    atomicAdd(&arr[sysid], (unsigned long long)(long long)(int)v);
   }
 }
 
@@ -683,6 +683,12 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
     sys_add(st + kEmitU, o8, (emit && tag == 1) ? 1u : 0u, leader);
     sys_add(st + kEmitUnd, o8, (emit && tag == 0) ? 1u : 0u, leader);
     sys_add(a.count_sys + (size_t)((level + 1) % 3) * a.B, sysid, (unsigned)n_push, leader);
+    if (a.pending_sys) {
+      // boxes still to step: + children pushed - this box (two's complement)
+      sys_add(a.pending_sys, sysid, (unsigned)(n_push - 1), leader);
+      const bool dropped = (idx < cnt) && !valid && r == 0;  // over the budget
+      sys_add(a.pending_sys, sysid, 0xFFFFFFFFu, dropped);
+    }
   }
   sc.s[kProcessed] += __popcll(__ballot(leader));
   sc.s[kExclEval] += __popcll(__ballot(leader && excluded));

@@ -86,6 +86,7 @@ struct SolveArgs {
   int level0;      // index of the first level of this launch (continuing searches)
   int slot_out_cap;  // > 0: each system emits into its own region of this many boxes
   unsigned long long* slot_out_count;  // [B] boxes emitted per system (regions)
+  unsigned long long* pending_sys;     // [B] boxes per system still to step (or null)
 };
 
 // Layout of the diagnostic dump of one step (doubles), n = system size:

@@ -38,6 +38,8 @@ def run(name):
         "hi": [[float(v).hex() for v in row] for row in r.hi],
         "tag": [int(v) for v in r.tag],
     }
+    # boxes stepped while (or when becoming) proven: the proof chains
+    out["chains"] = [[[float(v).hex() for v in a] for a in c] for c in oracle.proof_chains(s, **kw)]
     with open(os.path.join(HERE, f"expected_{name}.json"), "w") as fh:
         json.dump(out, fh, indent=1)
     print(name, r.status, r.stats, f"{dt:.1f}s", flush=True)

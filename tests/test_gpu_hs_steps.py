@@ -83,3 +83,28 @@ def test_single_steps_match_oracle(gpu_ctx, oracle_lib, name, make, center):
               f"  device {[float(v).hex() for v in a]}\n  oracle {[float(v).hex() for v in b]}\n"
               f"  lo={[float(v).hex() for v in lo]}\n  hi={[float(v).hex() for v in hi]}", flush=True)
     assert first is None
+
+
+@pytest.mark.parametrize("name,make", [("banded12_s1", lambda: W.banded(1)), ("banded12_s0", lambda: W.banded(0)),
+                                       ("dense6_s0", lambda: W.dense_planted(0))])
+def test_proof_chain_steps_match_oracle(gpu_ctx, oracle_lib, name, make):
+    """Replays the oracle's proof-chain boxes of a full-size solve one step at a
+    time on the device: every contracted box bit-identical."""
+    import paper_1802_00330_amd as P
+    path = os.path.join(os.path.dirname(__file__), "golden", f"expected_{name}.json")
+    g = json.load(open(path))
+    if "chains" not in g:
+        pytest.skip("no stored chain")
+    s = make()
+    for k, c in enumerate(g["chains"]):
+        lo, hi, elo, ehi = (np.array([float.fromhex(v) for v in a]) for a in c)
+        dev = P.ibb_debug_step(gpu_ctx, s, lo, hi)
+        st, ref = oracle_lib.hs_trace(s, lo, hi)
+        n = s.n
+        d = _compare(dev, ref, n)
+        X = dev[6 * n * n + 6 * n: 6 * n * n + 8 * n].reshape(n, 2)
+        if d is not None or not (np.array_equal(X[:, 0], elo) and np.array_equal(X[:, 1], ehi)):
+            print(f"[chain] {name} step {k}: first differing field {d and d[0]} idx {d and list(d[1])}\n"
+                  f"  device {d and [float(v).hex() for v in d[2]]}\n  oracle {d and [float(v).hex() for v in d[3]]}\n"
+                  f"  lo={[float(v).hex() for v in lo]}\n  hi={[float(v).hex() for v in hi]}", flush=True)
+        assert d is None, (name, k, d and d[0])
