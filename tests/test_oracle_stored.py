@@ -1,0 +1,29 @@
+"""The stored oracle results are reproducible: re-running the oracle's single
+contraction step on the stored proof-chain boxes gives the stored boxes (a
+check that the oracle computes the same on any host)."""
+import glob
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+MAKERS = {"dense6_s0": lambda: W.dense_planted(0), "dense6_s1": lambda: W.dense_planted(1),
+          "banded12_s0": lambda: W.banded(0), "banded12_s1": lambda: W.banded(1)}
+
+
+@pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(os.path.dirname(__file__), "golden",
+                                                                "expected_*.json"))))
+def test_stored_chains_reproduce(oracle_lib, path):
+    g = json.load(open(path))
+    if "chains" not in g:
+        pytest.skip("no chains stored")
+    s = MAKERS[g["case"]]()
+    for k, c in enumerate(g["chains"]):
+        lo, hi, elo, ehi = (np.array([float.fromhex(v) for v in a]) for a in c)
+        st, nlo, nhi, u = oracle_lib.hs(s, lo, hi)
+        bad = np.nonzero((nlo != elo) | (nhi != ehi))[0]
+        assert bad.size == 0, (g["case"], k, [(int(i), float(nlo[i]).hex(), float(elo[i]).hex(),
+                                               float(nhi[i]).hex(), float(ehi[i]).hex()) for i in bad[:4]])
