@@ -208,6 +208,28 @@ int64_t ibb_last_level_sizes(ibb_ctx* ctx, int64_t* sizes, int64_t cap);
  * Returns -1 if no solve was enqueued. */
 double ibb_last_kernel_ms(ibb_ctx* ctx);
 
+/* One round of the search (Alg. 1: a round set of boxes, each through the
+ * exclusion test of Def. 2, the contraction of Alg. 3 and the bisection of
+ * Alg. 2, exactly as inside ibb_solve) on `count` caller-given boxes.
+ * All arrays are host memory owned by the caller, boxes row-major [count][n]:
+ *   lo, hi    the boxes;
+ *   rec       one record per box: bit 0 = uniqueness already proven (the box
+ *             skips the exclusion test), bits 8..15 = recontractions so far;
+ *             other bits must be zero;
+ *   child_*   the next round's boxes and records, at most child_cap;
+ *   emit_*    boxes of width <= params->tol (or that cannot be split), with
+ *             tag 1 = proven unique root, at most emit_cap.
+ * The order of children and of emitted boxes is unspecified (compare as
+ * multisets).  params->max_boxes does not apply.  *n_child and *n_emit get the
+ * counts; when either exceeds its capacity IBB_ERR_OUTPUT_CAPACITY is
+ * returned and the outputs are not written.  stats (may be NULL) gets the
+ * round's counters.  Synchronous; uses the context's workspace. */
+int ibb_round(ibb_ctx* ctx, const ibb_system* sys, const ibb_params* params, int64_t count,
+              const double* lo, const double* hi, const uint32_t* rec, double* child_lo,
+              double* child_hi, uint32_t* child_rec, int64_t child_cap, int64_t* n_child,
+              double* emit_lo, double* emit_hi, uint8_t* emit_tag, int64_t emit_cap,
+              int64_t* n_emit, ibb_stats* stats);
+
 /* Diagnostics: run the search step on the single box [lo, hi] (one tree
  * level) and copy its intermediates to `dump` (host, >= 6n^2 + 8n + 4
  * doubles): J(X) [n][n][2], F(mid X) [n][2], the single-precision mid J

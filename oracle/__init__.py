@@ -64,6 +64,9 @@ def lib():
         L.oracle_solve.restype = C.c_int
         L.oracle_solve.argtypes = [C.c_int, p, p, p, p, p, d, i64, i32, i32, d, d,
                                    p, p, p, i64, p, p, C.c_int, C.c_uint64]
+        L.oracle_round.restype = C.c_int
+        L.oracle_round.argtypes = [C.c_int, p, p, p, i64, p, p, p, d, i32, i32, d, d,
+                                   p, p, p, i64, p, p, p, p, i64, p, p]
         _lib = L
     return _lib
 
@@ -201,3 +204,45 @@ def solve(s, tol: Optional[float] = None, max_boxes: int = 10_000_000, split_mod
         m = int(nout.value) if st == OK else 0
         return Result(st, olo[:m].copy(), ohi[:m].copy(), otag[:m].copy(),
                       dict(zip(STATS_FIELDS, (int(v) for v in stats))))
+
+
+@dataclass
+class Round:
+    status: int
+    child_lo: np.ndarray   # [c, n], in push order
+    child_hi: np.ndarray
+    child_rec: np.ndarray  # [c] uint32: bit 0 proven, bits 8-15 recontraction count
+    emit_lo: np.ndarray    # [e, n], in emission order
+    emit_hi: np.ndarray
+    emit_tag: np.ndarray   # [e] uint8
+    stats: dict
+
+
+def round_step(s, lo, hi, rec=None, tol: Optional[float] = None, split_mode: int = SPLIT_WIDEST,
+               max_recontract: int = 16, recontract_ratio: float = 0.5,
+               hs_max_width: float = float("inf")) -> Round:
+    """One round of the search on the boxes lo[b], hi[b] (see oracle_round)."""
+    to, ex, co = _sys_arrays(s)
+    lo = np.ascontiguousarray(np.asarray(lo, dtype=np.float64).reshape(-1, s.n))
+    hi = np.ascontiguousarray(np.asarray(hi, dtype=np.float64).reshape(-1, s.n))
+    m = lo.shape[0]
+    rec = np.zeros(m, dtype=np.uint32) if rec is None else np.ascontiguousarray(rec, dtype=np.uint32)
+    tol = s.tol if tol is None else tol
+    ccap, ecap = max(4 * m, 16), max(m, 16)
+    while True:
+        clo, chi = np.zeros((ccap, s.n)), np.zeros((ccap, s.n))
+        crec = np.zeros(ccap, dtype=np.uint32)
+        elo, ehi = np.zeros((ecap, s.n)), np.zeros((ecap, s.n))
+        etag = np.zeros(ecap, dtype=np.uint8)
+        nc, ne = C.c_int64(0), C.c_int64(0)
+        stats = np.zeros(8, dtype=np.int64)
+        st = lib().oracle_round(s.n, _ptr(to), _ptr(ex), _ptr(co), int(m), _ptr(lo), _ptr(hi), _ptr(rec),
+                                float(tol), int(split_mode), int(max_recontract), float(recontract_ratio),
+                                float(hs_max_width), _ptr(clo), _ptr(chi), _ptr(crec), int(ccap), C.byref(nc),
+                                _ptr(elo), _ptr(ehi), _ptr(etag), int(ecap), C.byref(ne), _ptr(stats))
+        if st == ERR_OUTPUT_CAPACITY:
+            ccap, ecap = max(ccap, int(nc.value)), max(ecap, int(ne.value))
+            continue
+        c, e = (int(nc.value), int(ne.value)) if st == OK else (0, 0)
+        return Round(st, clo[:c].copy(), chi[:c].copy(), crec[:c].copy(), elo[:e].copy(), ehi[:e].copy(),
+                     etag[:e].copy(), dict(zip(STATS_FIELDS, (int(v) for v in stats))))

@@ -754,6 +754,130 @@ static void chain_record(const ival* X, const ival* Xn, int n) {
   g_chain_len++;
 }
 
+/* One box through steps S1-S7 of the search (Alg. 1 with the contraction of
+ * Alg. 3 and the bisection of Alg. 2): counters in S, children pushed on st,
+ * boxes of width <= tol appended to out. */
+static int step_box(const osys* s, const oparams* p, const obox* b, ostack* st, olist* out, ostats* S) {
+  const int n = s->n;
+  /* Exclusion test (Def. 2): X holds no root if some F_i(X) excludes 0. */
+  if (!b->proven) {
+    int excluded = 0;
+    for (int i = 0; i < n && !excluded; ++i) {
+      ival f = eval_f(s, i, b->X);
+      if (f.lo > 0 || f.hi < 0) excluded = 1;
+    }
+    if (excluded) {
+      S->excluded_eval++;
+      return OR_OK;
+    }
+  }
+
+  /* Contraction (Alg. 3), unless the box is wider than hs_max_width. */
+  double w = box_width(b->X, n);
+  ival Xn[OR_MAX_N];
+  int u = 0;
+  int hs = HS_SKIPPED;
+  if (!(w > p->hs_max_width)) hs = hs_step(s, b->X, Xn, &u);
+  if (hs == HS_EMPTY) {
+    S->excluded_hs++;
+    return OR_OK;
+  }
+  if (hs == HS_SKIPPED) {
+    S->hs_skipped++;
+    for (int k = 0; k < n; ++k) Xn[k] = b->X[k];
+    u = 0;
+  }
+  int proven = b->proven || u;
+  if (proven) chain_record(b->X, Xn, n);
+  double wn = box_width(Xn, n);
+
+  if (wn <= p->tol) {
+    if (emit(out, Xn, n, proven ? 1 : 0)) return OR_ERR_NO_MEMORY;
+    if (proven) S->emitted_unique++; else S->emitted_undecided++;
+    return OR_OK;
+  }
+  if (proven) {
+    if (wn < w && b->rc + 1 < p->max_recontract) {
+      obox c;
+      memset(&c, 0, sizeof c);
+      for (int k = 0; k < n; ++k) c.X[k] = Xn[k];
+      c.proven = 1;
+      c.rc = b->rc + 1;
+      if (push(st, &c)) return OR_ERR_NO_MEMORY;
+      S->recontracted++;
+    } else {
+      if (emit(out, Xn, n, 1)) return OR_ERR_NO_MEMORY;
+      S->emitted_unique++;
+    }
+    return OR_OK;
+  }
+  if (wn <= rd_mul(p->recontract_ratio, w) && b->rc + 1 < p->max_recontract) {
+    obox c;
+    memset(&c, 0, sizeof c);
+    for (int k = 0; k < n; ++k) c.X[k] = Xn[k];
+    c.proven = 0;
+    c.rc = b->rc + 1;
+    if (push(st, &c)) return OR_ERR_NO_MEMORY;
+    S->recontracted++;
+    return OR_OK;
+  }
+
+  /* Bisection (Alg. 2 splits every coordinate at its midpoint; the default
+   * mode splits only the widest coordinate, first index on ties). */
+  if (p->split_mode == OR_SPLIT_WIDEST) {
+    int kk = 0;
+    double best = i_width(Xn[0]);
+    for (int k = 1; k < n; ++k) {
+      double wk = i_width(Xn[k]);
+      if (wk > best) {
+        best = wk;
+        kk = k;
+      }
+    }
+    double m = i_mid(Xn[kk]);
+    if (!(m > Xn[kk].lo && m < Xn[kk].hi)) {
+      if (emit(out, Xn, n, 0)) return OR_ERR_NO_MEMORY;
+      S->emitted_undecided++;
+      return OR_OK;
+    }
+    obox c;
+    memset(&c, 0, sizeof c);
+    for (int k = 0; k < n; ++k) c.X[k] = Xn[k];
+    c.X[kk] = iv(Xn[kk].lo, m);
+    if (push(st, &c)) return OR_ERR_NO_MEMORY;
+    c.X[kk] = iv(m, Xn[kk].hi);
+    if (push(st, &c)) return OR_ERR_NO_MEMORY;
+    S->bisected++;
+  } else {
+    int split[OR_MAX_N], ns = 0;
+    double mids[OR_MAX_N];
+    for (int k = 0; k < n; ++k) {
+      double m = i_mid(Xn[k]);
+      if (m > Xn[k].lo && m < Xn[k].hi) {
+        split[ns++] = k;
+        mids[k] = m;
+      }
+    }
+    if (ns == 0) {
+      if (emit(out, Xn, n, 0)) return OR_ERR_NO_MEMORY;
+      S->emitted_undecided++;
+      return OR_OK;
+    }
+    for (uint32_t bits = 0; bits < (1u << ns); ++bits) {
+      obox c;
+      memset(&c, 0, sizeof c);
+      for (int k = 0; k < n; ++k) c.X[k] = Xn[k];
+      for (int q = 0; q < ns; ++q) {
+        int k = split[q];
+        c.X[k] = ((bits >> q) & 1) ? iv(mids[k], Xn[k].hi) : iv(Xn[k].lo, mids[k]);
+      }
+      if (push(st, &c)) return OR_ERR_NO_MEMORY;
+    }
+    S->bisected++;
+  }
+  return OR_OK;
+}
+
 /* Solve: returns a status; on success the sorted boxes and tags.
  * order: 0 = last in first out, 1 = first in first out, 2 = random (seeded).
  * stats_out: 8 int64 counters (see ostats). */
@@ -803,123 +927,8 @@ int oracle_solve(int n, const int32_t* term_off, const uint8_t* expo, const doub
       break;
     }
 
-    /* Exclusion test (Def. 2): X holds no root if some F_i(X) excludes 0. */
-    if (!b.proven) {
-      int excluded = 0;
-      for (int i = 0; i < n && !excluded; ++i) {
-        ival f = eval_f(&s, i, b.X);
-        if (f.lo > 0 || f.hi < 0) excluded = 1;
-      }
-      if (excluded) {
-        S.excluded_eval++;
-        continue;
-      }
-    }
-
-    /* Contraction (Alg. 3), unless the box is wider than hs_max_width. */
-    double w = box_width(b.X, n);
-    ival Xn[OR_MAX_N];
-    int u = 0;
-    int hs = HS_SKIPPED;
-    if (!(w > p.hs_max_width)) hs = hs_step(&s, b.X, Xn, &u);
-    if (hs == HS_EMPTY) {
-      S.excluded_hs++;
-      continue;
-    }
-    if (hs == HS_SKIPPED) {
-      S.hs_skipped++;
-      for (int k = 0; k < n; ++k) Xn[k] = b.X[k];
-      u = 0;
-    }
-    int proven = b.proven || u;
-    if (proven) chain_record(b.X, Xn, n);
-    double wn = box_width(Xn, n);
-
-    if (wn <= p.tol) {
-      if (emit(&out, Xn, n, proven ? 1 : 0)) { status = OR_ERR_NO_MEMORY; break; }
-      if (proven) S.emitted_unique++; else S.emitted_undecided++;
-      continue;
-    }
-    if (proven) {
-      if (wn < w && b.rc + 1 < p.max_recontract) {
-        obox c;
-        memset(&c, 0, sizeof c);
-        for (int k = 0; k < n; ++k) c.X[k] = Xn[k];
-        c.proven = 1;
-        c.rc = b.rc + 1;
-        if (push(&st, &c)) { status = OR_ERR_NO_MEMORY; break; }
-        S.recontracted++;
-      } else {
-        if (emit(&out, Xn, n, 1)) { status = OR_ERR_NO_MEMORY; break; }
-        S.emitted_unique++;
-      }
-      continue;
-    }
-    if (wn <= rd_mul(p.recontract_ratio, w) && b.rc + 1 < p.max_recontract) {
-      obox c;
-      memset(&c, 0, sizeof c);
-      for (int k = 0; k < n; ++k) c.X[k] = Xn[k];
-      c.proven = 0;
-      c.rc = b.rc + 1;
-      if (push(&st, &c)) { status = OR_ERR_NO_MEMORY; break; }
-      S.recontracted++;
-      continue;
-    }
-
-    /* Bisection (Alg. 2 splits every coordinate at its midpoint; the default
-     * mode splits only the widest coordinate, first index on ties). */
-    if (p.split_mode == OR_SPLIT_WIDEST) {
-      int kk = 0;
-      double best = i_width(Xn[0]);
-      for (int k = 1; k < n; ++k) {
-        double wk = i_width(Xn[k]);
-        if (wk > best) {
-          best = wk;
-          kk = k;
-        }
-      }
-      double m = i_mid(Xn[kk]);
-      if (!(m > Xn[kk].lo && m < Xn[kk].hi)) {
-        if (emit(&out, Xn, n, 0)) { status = OR_ERR_NO_MEMORY; break; }
-        S.emitted_undecided++;
-        continue;
-      }
-      obox c;
-      memset(&c, 0, sizeof c);
-      for (int k = 0; k < n; ++k) c.X[k] = Xn[k];
-      c.X[kk] = iv(Xn[kk].lo, m);
-      if (push(&st, &c)) { status = OR_ERR_NO_MEMORY; break; }
-      c.X[kk] = iv(m, Xn[kk].hi);
-      if (push(&st, &c)) { status = OR_ERR_NO_MEMORY; break; }
-      S.bisected++;
-    } else {
-      int split[OR_MAX_N], ns = 0;
-      double mids[OR_MAX_N];
-      for (int k = 0; k < n; ++k) {
-        double m = i_mid(Xn[k]);
-        if (m > Xn[k].lo && m < Xn[k].hi) {
-          split[ns++] = k;
-          mids[k] = m;
-        }
-      }
-      if (ns == 0) {
-        if (emit(&out, Xn, n, 0)) { status = OR_ERR_NO_MEMORY; break; }
-        S.emitted_undecided++;
-        continue;
-      }
-      for (uint32_t bits = 0; bits < (1u << ns); ++bits) {
-        obox c;
-        memset(&c, 0, sizeof c);
-        for (int k = 0; k < n; ++k) c.X[k] = Xn[k];
-        for (int q = 0; q < ns; ++q) {
-          int k = split[q];
-          c.X[k] = ((bits >> q) & 1) ? iv(mids[k], Xn[k].hi) : iv(Xn[k].lo, mids[k]);
-        }
-        if (push(&st, &c)) { status = OR_ERR_NO_MEMORY; break; }
-      }
-      if (status != OR_OK) break;
-      S.bisected++;
-    }
+    status = step_box(&s, &p, &b, &st, &out, &S);
+    if (status != OR_OK) break;
   }
 
   if (stats_out) {
@@ -945,6 +954,76 @@ int oracle_solve(int n, const int32_t* term_off, const uint8_t* expo, const doub
           out_hi[e * n + k] = out.a[e].X[k].hi;
         }
         out_tag[e] = out.a[e].tag;
+      }
+    }
+  }
+  free(st.a);
+  free(out.a);
+  return status;
+}
+
+/* One round of the search on a caller-given list of boxes (the boxes of one
+ * round set of Alg. 1, each through step_box): the children in the order they
+ * are pushed, the boxes of width <= tol in the order they are emitted, neither
+ * sorted nor made canonical.  rec per box: bit 0 proven, bits 8-15 the
+ * recontraction count; the same record is written for each child.  No budget
+ * applies.  n_child and n_emit receive the counts also when they exceed the
+ * capacities (then OR_ERR_OUTPUT_CAPACITY is returned and nothing is copied). */
+int oracle_round(int n, const int32_t* term_off, const uint8_t* expo, const double* coef, int64_t count,
+                 const double* lo, const double* hi, const uint32_t* rec, double tol, int32_t split_mode,
+                 int32_t max_recontract, double recontract_ratio, double hs_max_width, double* child_lo,
+                 double* child_hi, uint32_t* child_rec, int64_t child_cap, int64_t* n_child, double* emit_lo,
+                 double* emit_hi, uint8_t* emit_tag, int64_t emit_cap, int64_t* n_emit, int64_t* stats_out) {
+  oparams p = {tol, 1, split_mode, max_recontract, recontract_ratio, hs_max_width};
+  ostats S;
+  memset(&S, 0, sizeof S);
+  *n_child = 0;
+  *n_emit = 0;
+  if (count < 0) return OR_ERR_INVALID_ARG;
+  for (int64_t b = 0; b < count; ++b)
+    if (!valid_input(n, term_off, expo, coef, lo + b * n, hi + b * n, &p)) return OR_ERR_INVALID_ARG;
+  if (count == 0) {
+    /* no box to check: validate the system and parameters on a zero box */
+    double z[OR_MAX_N] = {0};
+    if (!valid_input(n, term_off, expo, coef, z, z, &p)) return OR_ERR_INVALID_ARG;
+  }
+  osys s = make_sys(n, term_off, expo, coef);
+  ostack st = {0};
+  olist out = {0};
+  int status = OR_OK;
+  for (int64_t b = 0; b < count && status == OR_OK; ++b) {
+    obox x;
+    memset(&x, 0, sizeof x);
+    for (int k = 0; k < n; ++k) x.X[k] = iv(lo[b * n + k], hi[b * n + k]);
+    x.proven = (int)(rec[b] & 1u);
+    x.rc = (int)((rec[b] >> 8) & 0xFFu);
+    S.processed++;
+    status = step_box(&s, &p, &x, &st, &out, &S);
+  }
+  if (stats_out) {
+    int64_t v[8] = {S.processed, S.excluded_eval, S.excluded_hs, S.hs_skipped, S.recontracted,
+                    S.bisected, S.emitted_unique, S.emitted_undecided};
+    memcpy(stats_out, v, sizeof v);
+  }
+  if (status == OR_OK) {
+    *n_child = (int64_t)st.len;
+    *n_emit = (int64_t)out.len;
+    if ((int64_t)st.len > child_cap || (int64_t)out.len > emit_cap) {
+      status = OR_ERR_OUTPUT_CAPACITY;
+    } else {
+      for (size_t c = 0; c < st.len; ++c) {
+        for (int k = 0; k < n; ++k) {
+          child_lo[c * n + k] = st.a[c].X[k].lo;
+          child_hi[c * n + k] = st.a[c].X[k].hi;
+        }
+        child_rec[c] = (uint32_t)(st.a[c].proven ? 1u : 0u) | ((uint32_t)st.a[c].rc << 8);
+      }
+      for (size_t e = 0; e < out.len; ++e) {
+        for (int k = 0; k < n; ++k) {
+          emit_lo[e * n + k] = out.a[e].X[k].lo;
+          emit_hi[e * n + k] = out.a[e].X[k].hi;
+        }
+        emit_tag[e] = out.a[e].tag;
       }
     }
   }

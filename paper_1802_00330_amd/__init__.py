@@ -33,7 +33,7 @@ EXPORTS = ("ibb_ctx_create", "ibb_ctx_destroy", "ibb_strerror", "ibb_params_defa
            "ibb_workspace_size", "ibb_solve_async", "ibb_last_level_sizes", "ibb_last_kernel_ms",
            "ibb_selftest_ops", "ibb_debug_step", "ibb_solve_batch", "ibb_server_config_default",
            "ibb_server_create", "ibb_server_destroy", "ibb_server_submit", "ibb_server_step", "ibb_server_poll",
-           "ibb_server_cancel", "ibb_server_pending")
+           "ibb_server_cancel", "ibb_server_pending", "ibb_round")
 
 
 class IbbSystem(C.Structure):
@@ -104,6 +104,9 @@ def load_library(path: str = LIB_PATH):
     L.ibb_server_pending.argtypes = [p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.ibb_debug_step.restype = C.c_int
     L.ibb_debug_step.argtypes = [p, C.POINTER(IbbSystem), p, p, C.POINTER(IbbParams), p, i64]
+    L.ibb_round.restype = C.c_int
+    L.ibb_round.argtypes = [p, C.POINTER(IbbSystem), C.POINTER(IbbParams), i64, p, p, p, p, p, p, i64,
+                            C.POINTER(C.c_int64), p, p, p, i64, C.POINTER(C.c_int64), C.POINTER(IbbStats)]
     _lib = L
     return L
 
@@ -297,6 +300,48 @@ def ibb_debug_step(ctx: Context, s, lo, hi, params: Optional[IbbParams] = None) 
     if st != OK:
         raise RuntimeError(f"ibb_debug_step: {ibb_strerror(st)}")
     return dump
+
+
+@dataclass
+class Round:
+    child_lo: np.ndarray   # [c, n]
+    child_hi: np.ndarray
+    child_rec: np.ndarray  # [c] uint32: bit 0 proven, bits 8-15 recontraction count
+    emit_lo: np.ndarray    # [e, n]
+    emit_hi: np.ndarray
+    emit_tag: np.ndarray   # [e] uint8
+    stats: dict
+
+
+def ibb_round(ctx: Context, s, lo, hi, rec=None, params: Optional[IbbParams] = None) -> Round:
+    """One round of the search on the boxes lo[b], hi[b] (see include/ibb.h);
+    children and emitted boxes in unspecified order."""
+    ref = _SysRef(s)
+    lo = np.ascontiguousarray(np.asarray(lo, dtype=np.float64).reshape(-1, s.n))
+    hi = np.ascontiguousarray(np.asarray(hi, dtype=np.float64).reshape(-1, s.n))
+    m = lo.shape[0]
+    rec = np.zeros(m, dtype=np.uint32) if rec is None else np.ascontiguousarray(rec, dtype=np.uint32)
+    params = params or make_params(s.tol)
+    ccap, ecap = max(4 * m, 16), max(m, 16)
+    L = load_library()
+    while True:
+        clo, chi = np.zeros((ccap, s.n)), np.zeros((ccap, s.n))
+        crec = np.zeros(ccap, dtype=np.uint32)
+        elo, ehi = np.zeros((ecap, s.n)), np.zeros((ecap, s.n))
+        etag = np.zeros(ecap, dtype=np.uint8)
+        nc, ne = C.c_int64(0), C.c_int64(0)
+        st_ = IbbStats()
+        st = L.ibb_round(ctx.handle, C.byref(ref.c), C.byref(params), m, _ptr(lo), _ptr(hi), _ptr(rec), _ptr(clo),
+                         _ptr(chi), _ptr(crec), ccap, C.byref(nc), _ptr(elo), _ptr(ehi), _ptr(etag), ecap,
+                         C.byref(ne), C.byref(st_))
+        if st == ERR_OUTPUT_CAPACITY:
+            ccap, ecap = max(ccap, int(nc.value)), max(ecap, int(ne.value))
+            continue
+        if st != OK:
+            raise RuntimeError(f"ibb_round: {ibb_strerror(st)}")
+        c, e = int(nc.value), int(ne.value)
+        return Round(clo[:c].copy(), chi[:c].copy(), crec[:c].copy(), elo[:e].copy(), ehi[:e].copy(),
+                     etag[:e].copy(), {f: int(getattr(st_, f)) for f in STATS_FIELDS})
 
 
 def ibb_solve_batch(ctx: Context, systems, params=None, cap: int = 1 << 16):

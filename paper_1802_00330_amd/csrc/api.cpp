@@ -8,6 +8,7 @@
 #include <deque>
 #include <map>
 #include <new>
+#include <limits>
 #include <vector>
 
 #include "../../include/ibb.h"
@@ -278,6 +279,57 @@ int persistent_geometry(ibb_ctx* ctx, const void* fn, size_t table_bytes, int G,
   return IBB_OK;
 }
 
+// The persistent search launch of one system over a partitioned workspace
+// whose control block and level-0 frontier are already in place.
+int launch_search(ibb_ctx* ctx, const Compiled& c, const ibb_params* p, char* ws, const WsLayout& L,
+                  long long frontier_cap, long long out_cap, long long max_boxes, hipStream_t s, int max_levels,
+                  double* d_dbg) {
+  const int n = c.n, G = c.G;
+  Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
+  SolveArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.blob = reinterpret_cast<const uint64_t*>(ws + L.blob);
+  a.front[0] = reinterpret_cast<double*>(ws + L.front0);
+  a.front[1] = reinterpret_cast<double*>(ws + L.front1);
+  a.meta[0] = reinterpret_cast<uint32_t*>(ws + L.meta0);
+  a.meta[1] = reinterpret_cast<uint32_t*>(ws + L.meta1);
+  a.front_cap = frontier_cap;
+  a.out_box = reinterpret_cast<double*>(ws + L.out_box);
+  a.out_tag = reinterpret_cast<uint32_t*>(ws + L.out_tag);
+  a.out_cap = out_cap;
+  a.ctrl = ctrl;
+  a.level_sizes = reinterpret_cast<long long*>(ws + L.level);
+  a.level_cap = kLevelCap;
+  a.tol = p->tol;
+  a.ratio = p->recontract_ratio;
+  a.hs_max_width = p->hs_max_width;
+  a.max_boxes = max_boxes;
+  a.split_mode = p->split_mode;
+  a.max_rc = p->max_recontract;
+  a.timeout_ticks = ctx->clock_khz * 1000LL * 20;  // 20 s per barrier wait
+  a.max_levels = max_levels;
+  a.dbg = d_dbg;
+  a.out_count = &ctrl->out_count;
+  a.out_stride = G;
+
+  const void* fn = solve_kernel_ptr(G, false);
+  const size_t tbytes = (table_lds_bytes(n, c.T, c.TD) + 15) & ~size_t(15);
+  int waves = 0, blocks = 0;
+  size_t lds = 0;
+  {
+    const int gst = persistent_geometry(ctx, fn, tbytes, G, &waves, &lds, &blocks);
+    if (gst) return gst;
+  }
+  a.nblocks = blocks;
+  void* args[] = {&a};
+  hipEventRecord(ctx->ev0, s);
+  if (hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(64 * waves), args, (unsigned)lds, s) != hipSuccess)
+    return IBB_ERR_DEVICE;
+  hipEventRecord(ctx->ev1, s);
+  ctx->timed_pending = true;
+  return IBB_OK;
+}
+
 // Enqueue one solve into a partitioned workspace; outputs to device arrays.
 int enqueue_solve(ibb_ctx* ctx, const Compiled& c, const double* lo, const double* hi,
                   const ibb_params* p, char* ws, const WsLayout& L, long long frontier_cap,
@@ -306,49 +358,12 @@ int enqueue_solve(ibb_ctx* ctx, const Compiled& c, const double* lo, const doubl
                   dlo, dlo + kMaxN, n, G) != hipSuccess)
     return IBB_ERR_DEVICE;
 
-  SolveArgs a;
-  std::memset(&a, 0, sizeof a);
-  a.blob = reinterpret_cast<const uint64_t*>(ws + L.blob);
-  a.front[0] = reinterpret_cast<double*>(ws + L.front0);
-  a.front[1] = reinterpret_cast<double*>(ws + L.front1);
-  a.meta[0] = reinterpret_cast<uint32_t*>(ws + L.meta0);
-  a.meta[1] = reinterpret_cast<uint32_t*>(ws + L.meta1);
-  a.front_cap = frontier_cap;
-  a.out_box = reinterpret_cast<double*>(ws + L.out_box);
-  a.out_tag = reinterpret_cast<uint32_t*>(ws + L.out_tag);
-  a.out_cap = out_cap;
-  a.ctrl = ctrl;
-  a.level_sizes = reinterpret_cast<long long*>(ws + L.level);
-  a.level_cap = kLevelCap;
-  a.tol = p->tol;
-  a.ratio = p->recontract_ratio;
-  a.hs_max_width = p->hs_max_width;
-  a.max_boxes = p->max_boxes;
-  a.split_mode = p->split_mode;
-  a.max_rc = p->max_recontract;
-  a.timeout_ticks = ctx->clock_khz * 1000LL * 20;  // 20 s per barrier wait
-  a.max_levels = max_levels;
-  a.dbg = d_dbg;
-  a.out_count = &ctrl->out_count;
-  a.out_stride = G;
-
-  const void* fn = solve_kernel_ptr(G, false);
-  const size_t tbytes = (table_lds_bytes(n, c.T, c.TD) + 15) & ~size_t(15);
-  int waves = 0, blocks = 0;
-  size_t lds = 0;
   {
-    const int gst = persistent_geometry(ctx, fn, tbytes, G, &waves, &lds, &blocks);
-    if (gst) return gst;
+    const int lst = launch_search(ctx, c, p, ws, L, frontier_cap, out_cap, p->max_boxes, s, max_levels, d_dbg);
+    if (lst) return lst;
   }
-  a.nblocks = blocks;
-  void* args[] = {&a};
-  hipEventRecord(ctx->ev0, s);
-  if (hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(64 * waves), args, (unsigned)lds, s) != hipSuccess)
-    return IBB_ERR_DEVICE;
-  hipEventRecord(ctx->ev1, s);
-  ctx->timed_pending = true;
-  if (launch_sort(s, a.out_box, a.out_tag, ctrl, n, G, out_cap, d_out_lo, d_out_hi, d_out_tag, out_cap) !=
-      hipSuccess)
+  if (launch_sort(s, reinterpret_cast<const double*>(ws + L.out_box), reinterpret_cast<const uint32_t*>(ws + L.out_tag),
+                  ctrl, n, G, out_cap, d_out_lo, d_out_hi, d_out_tag, out_cap) != hipSuccess)
     return IBB_ERR_DEVICE;
   if (launch_finalize(s, ctrl, out_cap, d_info) != hipSuccess) return IBB_ERR_DEVICE;
   return IBB_OK;
@@ -847,6 +862,100 @@ int ibb_debug_step(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const 
     st = IBB_ERR_DEVICE;
   hipFree(d_dbg);
   return st;
+}
+
+int ibb_round(ibb_ctx* ctx, const ibb_system* sys, const ibb_params* params, int64_t count, const double* lo,
+              const double* hi, const uint32_t* rec, double* child_lo, double* child_hi, uint32_t* child_rec,
+              int64_t child_cap, int64_t* n_child, double* emit_lo, double* emit_hi, uint8_t* emit_tag,
+              int64_t emit_cap, int64_t* n_emit, ibb_stats* stats) {
+  if (!ctx || !n_child || !n_emit || count < 0 || child_cap < 0 || emit_cap < 0) return IBB_ERR_INVALID_ARG;
+  if (count > 0 && (!lo || !hi || !rec)) return IBB_ERR_INVALID_ARG;
+  if (child_cap > 0 && (!child_lo || !child_hi || !child_rec)) return IBB_ERR_INVALID_ARG;
+  if (emit_cap > 0 && (!emit_lo || !emit_hi || !emit_tag)) return IBB_ERR_INVALID_ARG;
+  *n_child = 0;
+  *n_emit = 0;
+  if (!sys || sys->n < 1 || sys->n > IBB_MAX_N) return IBB_ERR_INVALID_ARG;
+  const int n = sys->n;
+  std::vector<double> zero(n, 0.0);
+  int st = validate(sys, zero.data(), zero.data(), params);
+  for (int64_t b = 0; b < count && !st; ++b) st = validate(sys, lo + b * n, hi + b * n, params);
+  if (st) return st;
+  for (int64_t b = 0; b < count; ++b)
+    if ((rec[b] & ~0xFF01u) != 0) return IBB_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return IBB_ERR_DEVICE;
+  Compiled c;
+  try {
+    compile(sys, c);
+  } catch (...) {
+    return IBB_ERR_NO_MEMORY;
+  }
+  const int G = c.G;
+  const long long fcap = std::max<long long>({count, child_cap, 1});
+  const long long ocap = std::max<long long>(emit_cap, 1);
+  const WsLayout L = ws_layout(n, c.blob.size(), fcap, ocap);
+  st = ensure_device(&ctx->ws, &ctx->ws_bytes, L.total);
+  if (st) return st;
+  char* ws = static_cast<char*>(ctx->ws);
+  // level 0: the caller's boxes in the device layout (G rows of (lo, -hi))
+  std::vector<double> front((size_t)std::max<long long>(count, 1) * G * 2, 0.0);
+  for (int64_t b = 0; b < count; ++b)
+    for (int k = 0; k < n; ++k) {
+      front[((size_t)b * G + k) * 2] = lo[b * n + k];
+      front[((size_t)b * G + k) * 2 + 1] = -hi[b * n + k];
+    }
+  Ctrl ctrl;
+  std::memset(&ctrl, 0, sizeof ctrl);
+  ctrl.count[0] = (unsigned long long)count;
+  hipStream_t s = ctx->stream;
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(ws + L.blob, c.blob.data(), 8 * c.blob.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(ws + L.ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice) != hipSuccess ||
+      (count > 0 &&
+       (hipMemcpy(ws + L.front0, front.data(), sizeof(double) * count * G * 2, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ws + L.meta0, rec, sizeof(uint32_t) * count, hipMemcpyHostToDevice) != hipSuccess)))
+    return IBB_ERR_DEVICE;
+  if (launch_prep(s, reinterpret_cast<uint64_t*>(ws + L.blob), nullptr, 1) != hipSuccess) return IBB_ERR_DEVICE;
+  st = launch_search(ctx, c, params, ws, L, fcap, ocap, std::numeric_limits<long long>::max(), s, 1, nullptr);
+  if (st) return st;
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(&ctrl, ws + L.ctrl, sizeof ctrl, hipMemcpyDeviceToHost) != hipSuccess)
+    return IBB_ERR_DEVICE;
+  if (ctrl.status != 0) return ctrl.status;
+  if (stats) {
+    long long info[kInfoLen] = {0};
+    for (int i = 0; i < 8; ++i) info[2 + i] = (long long)ctrl.stats[i];
+    info[10] = (long long)ctrl.levels;
+    info[11] = (long long)ctrl.max_frontier;
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    fill_stats(stats, info, ms);
+  }
+  const long long nc = (long long)ctrl.count[1], ne = (long long)ctrl.out_count;
+  *n_child = nc;
+  *n_emit = ne;
+  if (nc > child_cap || ne > emit_cap) return IBB_ERR_OUTPUT_CAPACITY;
+  std::vector<double> cb((size_t)nc * G * 2), eb((size_t)ne * G * 2);
+  std::vector<uint32_t> et((size_t)ne);
+  if ((nc > 0 &&
+       (hipMemcpy(cb.data(), ws + L.front1, sizeof(double) * cb.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(child_rec, ws + L.meta1, sizeof(uint32_t) * nc, hipMemcpyDeviceToHost) != hipSuccess)) ||
+      (ne > 0 &&
+       (hipMemcpy(eb.data(), ws + L.out_box, sizeof(double) * eb.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(et.data(), ws + L.out_tag, sizeof(uint32_t) * ne, hipMemcpyDeviceToHost) != hipSuccess)))
+    return IBB_ERR_DEVICE;
+  for (long long b = 0; b < nc; ++b)
+    for (int k = 0; k < n; ++k) {
+      child_lo[b * n + k] = cb[((size_t)b * G + k) * 2];
+      child_hi[b * n + k] = -cb[((size_t)b * G + k) * 2 + 1];
+    }
+  for (long long b = 0; b < ne; ++b) {
+    for (int k = 0; k < n; ++k) {
+      emit_lo[b * n + k] = eb[((size_t)b * G + k) * 2];
+      emit_hi[b * n + k] = -eb[((size_t)b * G + k) * 2 + 1];
+    }
+    emit_tag[b] = (uint8_t)et[b];
+  }
+  return IBB_OK;
 }
 
 int ibb_selftest_ops(ibb_ctx* ctx, int32_t op, int64_t n, const double* a, const double* b, double* out) {

@@ -103,8 +103,17 @@ def test_proof_chain_steps_match_oracle(gpu_ctx, oracle_lib, name, make):
         n = s.n
         d = _compare(dev, ref, n)
         X = dev[6 * n * n + 6 * n: 6 * n * n + 8 * n].reshape(n, 2)
-        if d is not None or not (np.array_equal(X[:, 0], elo) and np.array_equal(X[:, 1], ehi)):
+        R = ref[6 * n * n + 6 * n: 6 * n * n + 8 * n].reshape(n, 2)
+        same_chain = np.array_equal(X[:, 0], elo) and np.array_equal(X[:, 1], ehi)
+        if d is not None or not same_chain:
+            idx = np.nonzero((X[:, 0] != elo) | (X[:, 1] != ehi))[0][:4]
             print(f"[chain] {name} step {k}: first differing field {d and d[0]} idx {d and list(d[1])}\n"
                   f"  device {d and [float(v).hex() for v in d[2]]}\n  oracle {d and [float(v).hex() for v in d[3]]}\n"
+                  f"  X' differs from the stored chain at {idx.tolist()}: device "
+                  f"{[(float(X[i, 0]).hex(), float(X[i, 1]).hex()) for i in idx]} trace "
+                  f"{[(float(R[i, 0]).hex(), float(R[i, 1]).hex()) for i in idx]} chain "
+                  f"{[(float(elo[i]).hex(), float(ehi[i]).hex()) for i in idx]} flags {dev[-4:].tolist()} "
+                  f"{ref[-4:].tolist()}\n"
                   f"  lo={[float(v).hex() for v in lo]}\n  hi={[float(v).hex() for v in hi]}", flush=True)
         assert d is None, (name, k, d and d[0])
+        assert same_chain, (name, k)
