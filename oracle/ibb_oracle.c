@@ -45,6 +45,13 @@
 #define OR_SPLIT_WIDEST 0
 #define OR_SPLIT_ALL 1
 
+/* Every exported entry point leaves the caller's rounding mode as it found
+ * it: the interval operations below switch the mode per bound, and a caller
+ * (for example an interpreter evaluating its own floating-point expressions
+ * afterwards) must not inherit a directed mode. */
+static void restore_mode(const int* m) { fesetround(*m); }
+#define KEEP_CALLER_MODE const int keep_mode_ __attribute__((cleanup(restore_mode))) = fegetround()
+
 /* ------------------------------------------------------------------------- */
 /* Directed rounding of a single operation: eq (25)-(27).                      */
 /* The operands are read, the mode is set, the operation is performed and the  */
@@ -55,9 +62,10 @@
   double name(double a, double b) {                                   \
     volatile double x = a, y = b;                                     \
     volatile double r;                                                \
+    const int caller = fegetround();                                  \
     fesetround(mode);                                                 \
     r = expr;                                                         \
-    fesetround(FE_TONEAREST);                                         \
+    fesetround(caller);                                               \
     return r;                                                         \
   }
 
@@ -140,6 +148,7 @@ static ival i_mul(ival x, ival y) {
 }
 
 void oracle_i_mul(double a, double b, double c, double d, double* out) {
+  KEEP_CALLER_MODE;
   ival r = i_mul(iv(a, b), iv(c, d));
   out[0] = r.lo;
   out[1] = r.hi;
@@ -172,6 +181,7 @@ static ival i_pow(ival x, int p) {
 }
 
 void oracle_i_pow(double a, double b, int p, double* out) {
+  KEEP_CALLER_MODE;
   ival r = i_pow(iv(a, b), p);
   out[0] = r.lo;
   out[1] = r.hi;
@@ -220,6 +230,7 @@ static int i_div_ext(ival x, ival y, ival out[2]) {
 }
 
 int oracle_i_div_ext(double a, double b, double c, double d, double* out) {
+  KEEP_CALLER_MODE;
   ival p[2];
   int k = i_div_ext(iv(a, b), iv(c, d), p);
   for (int i = 0; i < k; ++i) {
@@ -295,6 +306,7 @@ static osys make_sys(int n, const int32_t* term_off, const uint8_t* expo, const 
 
 void oracle_eval_F(int n, const int32_t* term_off, const uint8_t* expo, const double* coef,
                    const double* lo, const double* hi, double* out_lo, double* out_hi) {
+  KEEP_CALLER_MODE;
   osys s = make_sys(n, term_off, expo, coef);
   ival X[OR_MAX_N];
   for (int k = 0; k < n; ++k) X[k] = iv(lo[k], hi[k]);
@@ -307,6 +319,7 @@ void oracle_eval_F(int n, const int32_t* term_off, const uint8_t* expo, const do
 
 void oracle_eval_J(int n, const int32_t* term_off, const uint8_t* expo, const double* coef,
                    const double* lo, const double* hi, double* out_lo, double* out_hi) {
+  KEEP_CALLER_MODE;
   osys s = make_sys(n, term_off, expo, coef);
   ival X[OR_MAX_N];
   for (int k = 0; k < n; ++k) X[k] = iv(lo[k], hi[k]);
@@ -327,6 +340,7 @@ void oracle_eval_J(int n, const int32_t* term_off, const uint8_t* expo, const do
 /* any non-finite value), in which case the contraction is skipped.            */
 /* ------------------------------------------------------------------------- */
 int oracle_fp32_inverse(int n, const float* Min, float* Y) {
+  KEEP_CALLER_MODE;
   float M[OR_MAX_N][OR_MAX_N];
   int perm[OR_MAX_N];
   fesetround(FE_TONEAREST);
@@ -578,6 +592,7 @@ static int hs_step(const osys* s, const ival* X, ival* Xn, int* unique) {
  * (6n^2 + 8n + 4 doubles, layout of tr_* above). */
 int oracle_hs_trace(int n, const int32_t* term_off, const uint8_t* expo, const double* coef,
                     const double* lo, const double* hi, double* trace) {
+  KEEP_CALLER_MODE;
   osys s = make_sys(n, term_off, expo, coef);
   ival X[OR_MAX_N], Xn[OR_MAX_N];
   for (int k = 0; k < n; ++k) X[k] = iv(lo[k], hi[k]);
@@ -591,6 +606,7 @@ int oracle_hs_trace(int n, const int32_t* term_off, const uint8_t* expo, const d
 
 int oracle_hs(int n, const int32_t* term_off, const uint8_t* expo, const double* coef,
               const double* lo, const double* hi, double* out_lo, double* out_hi, int* unique) {
+  KEEP_CALLER_MODE;
   osys s = make_sys(n, term_off, expo, coef);
   ival X[OR_MAX_N], Xn[OR_MAX_N];
   for (int k = 0; k < n; ++k) X[k] = iv(lo[k], hi[k]);
@@ -886,6 +902,7 @@ int oracle_solve(int n, const int32_t* term_off, const uint8_t* expo, const doub
                  int32_t split_mode, int32_t max_recontract, double recontract_ratio,
                  double hs_max_width, double* out_lo, double* out_hi, uint8_t* out_tag,
                  int64_t cap, int64_t* n_out, int64_t* stats_out, int order, uint64_t seed) {
+  KEEP_CALLER_MODE;
   oparams p = {tol, max_boxes, split_mode, max_recontract, recontract_ratio, hs_max_width};
   ostats S;
   memset(&S, 0, sizeof S);
@@ -974,6 +991,7 @@ int oracle_round(int n, const int32_t* term_off, const uint8_t* expo, const doub
                  int32_t max_recontract, double recontract_ratio, double hs_max_width, double* child_lo,
                  double* child_hi, uint32_t* child_rec, int64_t child_cap, int64_t* n_child, double* emit_lo,
                  double* emit_hi, uint8_t* emit_tag, int64_t emit_cap, int64_t* n_emit, int64_t* stats_out) {
+  KEEP_CALLER_MODE;
   oparams p = {tol, 1, split_mode, max_recontract, recontract_ratio, hs_max_width};
   ostats S;
   memset(&S, 0, sizeof S);

@@ -61,8 +61,24 @@ class System:
             yield self.coef[a:b], self.expo[a:b]
 
 
+_LIBC = None
+
+
+def _require_nearest():
+    """The generators round with the floating-point unit's current mode; a
+    mode other than round-to-nearest (left behind by some native library)
+    would change the coefficients, so it is refused."""
+    global _LIBC
+    if _LIBC is None:
+        import ctypes
+        _LIBC = ctypes.CDLL(None)
+    if _LIBC.fegetround() != 0:  # FE_TONEAREST
+        raise RuntimeError("workloads: the floating-point rounding mode is not round-to-nearest")
+
+
 def _pack(n: int, eqs: Sequence[Sequence[tuple]], lo, hi, tol, name, roots=()) -> System:
     """eqs[i] is a list of (coef, exponent tuple) in stored order."""
+    _require_nearest()
     term_off = np.zeros(n + 1, dtype=np.int32)
     coefs, expos = [], []
     for i, terms in enumerate(eqs):
