@@ -169,8 +169,8 @@ def main():
                     help="MiB copied by a plain device copy before the solves (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: the search has no multi-GPU path in this build "
-              "(see DESIGN.md for how it would shard).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: one process drives one device and the search has "
+              "no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -17,7 +17,8 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libibb.so")
+# IBB_LIBRARY may name another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("IBB_LIBRARY") or os.path.join(_HERE, "libibb.so")
 
 OK = 0
 ERR_INVALID_ARG, ERR_BUDGET, ERR_OUTPUT_CAPACITY, ERR_QUEUE_OVERFLOW = -1, -2, -3, -4
