@@ -16,7 +16,7 @@
 
 namespace ibb {
 // kernels.hip
-size_t scratch_bytes(int G);
+size_t scratch_bytes(int G, int jn, int rs);
 const void* solve_kernel_ptr(int G, bool multi);
 hipError_t launch_prep(hipStream_t s, uint64_t* blobs, const long long* blob_off, int B);
 hipError_t launch_batch_init(hipStream_t s, Ctrl* c, double* front0, uint32_t* meta0, uint32_t* sys0,
@@ -211,6 +211,7 @@ struct ibb_ctx {
   int device = 0;
   int num_cu = 0;
   size_t max_lds_block = 0;
+  size_t lds_per_cu = 0;
   long long clock_khz = 100000;
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, staged = nullptr;
@@ -261,21 +262,52 @@ int ensure_pinned(ibb_ctx* ctx, size_t need) {
 }
 
 // Launch geometry of a persistent kernel: waves per block, LDS, grid.
-int persistent_geometry(ibb_ctx* ctx, const void* fn, size_t table_bytes, int G, int* waves_out,
-                        size_t* lds_out, int* blocks_out) {
-  const size_t per_wave = scratch_bytes(G);
-  int waves = 4;
-  while (waves > 1 && table_bytes + per_wave * waves > ctx->max_lds_block) --waves;
-  const size_t lds = table_bytes + per_wave * waves;
-  if (lds > ctx->max_lds_block) return IBB_ERR_UNSUPPORTED;
-  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-    return IBB_ERR_DEVICE;
+// Workgroups of a persistent launch that are resident on one CU at once.
+// The occupancy query alone over-promises near the LDS limit (measured on
+// gfx950: three workgroups of 53,952 B were reported to fit the 160 KiB of a
+// CU, two were resident); LDS is therefore also counted in 2 KiB granules.
+int resident_per_cu(ibb_ctx* ctx, const void* fn, int threads, size_t lds) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * waves, lds) != hipSuccess || per_cu < 1)
-    return IBB_ERR_UNSUPPORTED;
-  *waves_out = waves;
-  *lds_out = lds;
-  *blocks_out = per_cu * ctx->num_cu;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) return 0;
+  const size_t granule = 2048;
+  const size_t rounded = (lds + granule - 1) / granule * granule;
+  if (rounded > 0 && ctx->lds_per_cu > 0) per_cu = std::min<int>(per_cu, (int)(ctx->lds_per_cu / rounded));
+  return per_cu;
+}
+
+// Launch geometry of a persistent kernel: waves per block, LDS, grid and the
+// row stride of the Jacobian scratch.  jn is the Jacobian dimension the
+// kernel sizes its scratch for (n for one system, G for a batch); the row
+// stride is jn + 1 unless the padding would cost a resident workgroup.
+struct Geometry {
+  int waves = 0, blocks = 0, jrs = 0;
+  size_t lds = 0;
+};
+
+int persistent_geometry(ibb_ctx* ctx, const void* fn, size_t table_bytes, int G, int jn, Geometry* out) {
+  Geometry best;
+  int best_per_cu = 0;
+  for (int rs : {jn + 1, jn}) {
+    const size_t per_wave = scratch_bytes(G, jn, rs);
+    int waves = 4;
+    while (waves > 1 && table_bytes + per_wave * waves > ctx->max_lds_block) --waves;
+    const size_t lds = table_bytes + per_wave * waves;
+    if (lds > ctx->max_lds_block) continue;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      return IBB_ERR_DEVICE;
+    const int per_cu = resident_per_cu(ctx, fn, 64 * waves, lds);
+    if (per_cu * waves > best_per_cu * best.waves) {
+      best_per_cu = per_cu;
+      best.waves = waves;
+      best.lds = lds;
+      best.jrs = rs;
+    }
+  }
+  if (best_per_cu < 1) return IBB_ERR_UNSUPPORTED;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)best.lds) != hipSuccess)
+    return IBB_ERR_DEVICE;
+  best.blocks = best_per_cu * ctx->num_cu;
+  *out = best;
   return IBB_OK;
 }
 
@@ -314,16 +346,17 @@ int launch_search(ibb_ctx* ctx, const Compiled& c, const ibb_params* p, char* ws
 
   const void* fn = solve_kernel_ptr(G, false);
   const size_t tbytes = (table_lds_bytes(n, c.T, c.TD) + 15) & ~size_t(15);
-  int waves = 0, blocks = 0;
-  size_t lds = 0;
+  Geometry geo;
   {
-    const int gst = persistent_geometry(ctx, fn, tbytes, G, &waves, &lds, &blocks);
+    const int gst = persistent_geometry(ctx, fn, tbytes, G, n, &geo);
     if (gst) return gst;
   }
-  a.nblocks = blocks;
+  a.nblocks = geo.blocks;
+  a.jrs = geo.jrs;
   void* args[] = {&a};
   hipEventRecord(ctx->ev0, s);
-  if (hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(64 * waves), args, (unsigned)lds, s) != hipSuccess)
+  if (hipLaunchCooperativeKernel(fn, dim3(geo.blocks), dim3(64 * geo.waves), args, (unsigned)geo.lds, s) !=
+      hipSuccess)
     return IBB_ERR_DEVICE;
   hipEventRecord(ctx->ev1, s);
   ctx->timed_pending = true;
@@ -562,13 +595,14 @@ extern "C" int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* system
       a.stats_sys = reinterpret_cast<unsigned long long*>(D(L.stats_sys));
       a.B = B;
       const void* fn = solve_kernel_ptr(G, true);
-      int waves = 0, blocks = 0;
-      size_t lds = 0;
-      st = persistent_geometry(ctx, fn, 0, G, &waves, &lds, &blocks);
+      Geometry geo;
+      st = persistent_geometry(ctx, fn, 0, G, G, &geo);
       if (st) return st;
-      a.nblocks = blocks;
+      a.nblocks = geo.blocks;
+      a.jrs = geo.jrs;
       void* args[] = {&a};
-      if (hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(64 * waves), args, (unsigned)lds, s) != hipSuccess)
+      if (hipLaunchCooperativeKernel(fn, dim3(geo.blocks), dim3(64 * geo.waves), args, (unsigned)geo.lds, s) !=
+          hipSuccess)
         return IBB_ERR_DEVICE;
     }
     hipEventRecord(ctx->ev1, s);
@@ -688,6 +722,7 @@ int ibb_ctx_create(int device, ibb_ctx** out) {
   }
   c->num_cu = prop.multiProcessorCount;
   c->max_lds_block = prop.sharedMemPerBlock;
+  c->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
     c->clock_khz = khz;
@@ -1345,13 +1380,14 @@ int ibb_server_step(ibb_server* sv) {
     a.pending_sys = sv->pending;
     a.B = S;
     const void* fn = solve_kernel_ptr(b.G, true);
-    int waves = 0, blocks = 0;
-    size_t lds = 0;
-    const int st = persistent_geometry(ctx, fn, 0, b.G, &waves, &lds, &blocks);
+    Geometry geo;
+    const int st = persistent_geometry(ctx, fn, 0, b.G, b.G, &geo);
     if (st) return st;
-    a.nblocks = blocks;
+    a.nblocks = geo.blocks;
+    a.jrs = geo.jrs;
     void* args[] = {&a};
-    if (hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(64 * waves), args, (unsigned)lds, s) != hipSuccess)
+    if (hipLaunchCooperativeKernel(fn, dim3(geo.blocks), dim3(64 * geo.waves), args, (unsigned)geo.lds, s) !=
+        hipSuccess)
       return IBB_ERR_DEVICE;
     any = true;
   }

@@ -193,18 +193,36 @@ __device__ __forceinline__ iv eval_partial(const LTable& t, int i, int k, const 
 }
 
 // ---------------------------------------------------------------------------
-// Per-wave scratch in LDS for the W = 64/G boxes of a tile.
+// Per-wave scratch in LDS for the W = 64/G boxes of a tile.  Each box's rows
+// are padded by one element so that the boxes of a wave (and, in the
+// Jacobian, the rows of a box) start on different LDS banks.
 // ---------------------------------------------------------------------------
 template <int G>
 struct Scratch {
   static constexpr int W = 64 / G;
-  iv X[W][G];      // current box
-  iv Xn[W][G];     // contracted box
-  iv D[W][G];      // X - mid X, then X' - mid X as the sweep advances
-  iv Fc[W][G];     // F at the expansion point
-  iv Xc[W][G];     // expansion point as degenerate intervals
-  iv J[W][G][G];   // interval Jacobian, row = equation
-  float row[W][G]; // broadcast buffer of the single-precision solver
+  iv X[W][G + 1];      // current box
+  iv Xn[W][G + 1];     // contracted box
+  iv D[W][G + 1];      // X - mid X, then X' - mid X as the sweep advances
+  iv Fc[W][G + 1];     // F at the expansion point
+  iv Xc[W][G + 1];     // expansion point as degenerate intervals
+  float row[W][G + 1]; // broadcast buffer of the single-precision solver
+};
+
+// The interval Jacobian of the W boxes follows the Scratch block: box g, row
+// r, column k at g * (jn * rs + 1) + r * rs + k, with jn = n for one system
+// (the area shrinks with n, which raises the number of resident waves), jn =
+// G for batches of systems of different sizes, and a row stride rs of jn or
+// jn + 1 (padding spreads the rows of a box over the LDS banks; the host drops
+// it when it would cost a resident workgroup).
+template <int G>
+__host__ __device__ constexpr size_t wave_scratch_bytes(int jn, int rs) {
+  return ((sizeof(Scratch<G>) + 15) / 16) * 16 + (size_t)(64 / G) * (jn * rs + 1) * sizeof(iv);
+}
+
+struct JView {
+  iv* p;
+  int gs, rs;  // box and row strides
+  __device__ __forceinline__ iv& operator()(int g, int r, int k) const { return p[g * gs + r * rs + k]; }
 };
 
 // Narrowing of the midpoint of J to single precision, round to nearest.  The
@@ -296,7 +314,8 @@ __device__ __forceinline__ void sys_add(unsigned long long* arr, uint32_t sysid,
 }
 
 template <int G, bool MULTI>
-__device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, Scratch<G>& S, long long base,
+__device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, Scratch<G>& S, const JView J,
+                          long long base,
                           long long cnt, int cur, int level, unsigned long long* next_count,
                           StepCounters& sc) {
   const int lane = __lane_id();
@@ -373,12 +392,12 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
     wave_lds_sync();
     // H2, H3: row r of J(X); F_r at the degenerate box [x, x]
     if (do_hs && row_ok) {
-      for (int k = 0; k < n; ++k) S.J[g][r][k] = eval_partial(T, r, k, S.X[g]);
+      for (int k = 0; k < n; ++k) J(g, r, k) = eval_partial(T, r, k, S.X[g]);
       S.Fc[g][r] = eval_equation(T, r, S.Xc[g]);
       if (dbg) {
         for (int k = 0; k < n; ++k) {
-          dbg[dbg_off_J(n) + (r * n + k) * 2] = S.J[g][r][k].lo;
-          dbg[dbg_off_J(n) + (r * n + k) * 2 + 1] = -S.J[g][r][k].nhi;
+          dbg[dbg_off_J(n) + (r * n + k) * 2] = J(g, r, k).lo;
+          dbg[dbg_off_J(n) + (r * n + k) * 2 + 1] = -J(g, r, k).nhi;
         }
         dbg[dbg_off_F(n) + 2 * r] = S.Fc[g][r].lo;
         dbg[dbg_off_F(n) + 2 * r + 1] = -S.Fc[g][r].nhi;
@@ -388,7 +407,7 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
     // H4: single-precision mid J, row r
     float M[G];
 #pragma unroll
-    for (int k = 0; k < G; ++k) M[k] = (do_hs && row_ok && k < n) ? narrow_rn(imid(S.J[g][r][k])) : 0.0f;
+    for (int k = 0; k < G; ++k) M[k] = (do_hs && row_ok && k < n) ? narrow_rn(imid(J(g, r, k))) : 0.0f;
     if (dbg && row_ok) {
 #pragma unroll
       for (int k = 0; k < G; ++k)
@@ -531,22 +550,22 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
 #pragma unroll
         for (int m = 0; m < G; ++m) {
           if (m < n && ((T.jnz[m] >> j) & 1u) && z[m] != 0.0f) {
-            const iv t = pmul((double)z[m], S.J[g][m][j]);
+            const iv t = pmul((double)z[m], J(g, m, j));
             pj = have ? iadd(pj, t) : t;
             have = true;
           }
         }
       }
       wave_lds_sync();
-      if (run && row_ok && j < n) S.J[g][pos][j] = pj;
+      if (run && row_ok && j < n) J(g, pos, j) = pj;
     }
     wave_lds_sync();
     if (dbg && run && row_ok) {
       dbg[dbg_off_g(n) + 2 * pos] = gv.lo;
       dbg[dbg_off_g(n) + 2 * pos + 1] = -gv.nhi;
       for (int j = 0; j < n; ++j) {
-        dbg[dbg_off_P(n) + (pos * n + j) * 2] = S.J[g][pos][j].lo;
-        dbg[dbg_off_P(n) + (pos * n + j) * 2 + 1] = -S.J[g][pos][j].nhi;
+        dbg[dbg_off_P(n) + (pos * n + j) * 2] = J(g, pos, j).lo;
+        dbg[dbg_off_P(n) + (pos * n + j) * 2 + 1] = -J(g, pos, j).nhi;
       }
     }
     // S_U = sum_{j > pos} P[pos][j] (X_j - x_j), j ascending
@@ -554,7 +573,7 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
     bool hasU = false;
     if (run && row_ok) {
       for (int j = pos + 1; j < n; ++j) {
-        const iv t = imul(S.J[g][pos][j], S.D[g][j]);
+        const iv t = imul(J(g, pos, j), S.D[g][j]);
         SU = hasU ? iadd(SU, t) : t;
         hasU = true;
       }
@@ -575,7 +594,7 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
         const double xc = S.Xc[g][i].lo;
         iv xn;
         bool inside = false;
-        const bool ok = gs_component(N, S.J[g][i][i], xc, S.X[g][i], xn, inside);
+        const bool ok = gs_component(N, J(g, i, i), xc, S.X[g][i], xn, inside);
         my_empty = !ok;
         my_unique = ok && inside;
         if (!ok) xn = S.X[g][i];
@@ -590,7 +609,7 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
       }
       wave_lds_sync();
       if (run && row_ok && pos > i) {
-        const iv t = imul(S.J[g][pos][i], S.D[g][i]);
+        const iv t = imul(J(g, pos, i), S.D[g][i]);
         SL = hasL ? iadd(SL, t) : t;
         hasL = true;
       }
@@ -830,8 +849,16 @@ __device__ __forceinline__ void grid_barrier(const SolveArgs& a, unsigned long l
   __threadfence();
 }
 
+// Resident waves per SIMD the register allocation aims for: three for one
+// system of up to 8 unknowns, whose n-sized scratch lets three fit in LDS.
 template <int G, bool MULTI>
-__global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
+struct Occupancy {
+  static constexpr int waves = (!MULTI && G <= 8) ? 3 : 2;
+};
+
+template <int G, bool MULTI>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Occupancy<G, MULTI>::waves)))
+solve_kernel(SolveArgs a) {
   set_fp64_round_down();
   extern __shared__ __align__(16) char smem[];
   LTable T{};
@@ -841,7 +868,10 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
     T = stage_table(a.blob, smem);
     table_bytes = align16(table_lds_bytes(d->n, d->T, d->TD));
   }
-  Scratch<G>* S = reinterpret_cast<Scratch<G>*>(smem + table_bytes) + (threadIdx.x / 64);
+  const int jn = MULTI ? G : reinterpret_cast<const SysDesc*>(a.blob)->n;
+  char* const wave_base = smem + table_bytes + (threadIdx.x / 64) * wave_scratch_bytes<G>(jn, a.jrs);
+  Scratch<G>* S = reinterpret_cast<Scratch<G>*>(wave_base);
+  const JView J{reinterpret_cast<iv*>(wave_base + ((sizeof(Scratch<G>) + 15) / 16) * 16), jn * a.jrs + 1, a.jrs};
   __syncthreads();
 
   constexpr int W = 64 / G;
@@ -884,7 +914,7 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
       if (lane == 0) base = atomicAdd(&c->claim[level % 3], (unsigned long long)W);
       base = __shfl(base, 0, 64);
       if (base >= cnt) break;
-      step_tile<G, MULTI>(a, T, *S, (long long)base, (long long)cnt, cur, level, next_count, sc);
+      step_tile<G, MULTI>(a, T, *S, J, (long long)base, (long long)cnt, cur, level, next_count, sc);
     }
     grid_barrier(a, target);
   }
@@ -1082,12 +1112,12 @@ __global__ void slot_sort_kernel(const double* box, const uint32_t* tag, const u
 // ---------------------------------------------------------------------------
 // Host-side launch helpers (called by the runtime in api.cpp).
 // ---------------------------------------------------------------------------
-size_t scratch_bytes(int G) {
+size_t scratch_bytes(int G, int jn, int rs) {
   switch (G) {
-    case 2: return sizeof(Scratch<2>);
-    case 4: return sizeof(Scratch<4>);
-    case 8: return sizeof(Scratch<8>);
-    default: return sizeof(Scratch<16>);
+    case 2: return wave_scratch_bytes<2>(jn, rs);
+    case 4: return wave_scratch_bytes<4>(jn, rs);
+    case 8: return wave_scratch_bytes<8>(jn, rs);
+    default: return wave_scratch_bytes<16>(jn, rs);
   }
 }
 

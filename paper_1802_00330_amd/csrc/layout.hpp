@@ -84,6 +84,7 @@ struct SolveArgs {
   int B;
   int out_stride;  // coordinates per output record (G for one system, kMaxN for batches)
   int level0;      // index of the first level of this launch (continuing searches)
+  int jrs;         // row stride (in intervals) of the per-box Jacobian in LDS
   int slot_out_cap;  // > 0: each system emits into its own region of this many boxes
   unsigned long long* slot_out_count;  // [B] boxes emitted per system (regions)
   unsigned long long* pending_sys;     // [B] boxes per system still to step (or null)
