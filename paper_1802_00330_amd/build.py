@@ -1,6 +1,7 @@
 """Build step of the HIP library: compiles csrc/*.hip and csrc/*.cpp with hipcc
 for gfx950 into libibb.so next to this file."""
 import os
+import re
 import subprocess
 import sys
 
@@ -21,6 +22,21 @@ FLAGS = [
 SOURCES = ["kernels.hip", "api.cpp"]
 
 
+def check_no_scratch(remarks: str) -> None:
+    """The persistent search kernels must keep every value in registers or
+    LDS: a variant that spilled to scratch memory gave run-to-run different
+    trees, so a build whose search kernels use scratch is rejected."""
+    current = None
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            current = m.group(1)
+            continue
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and current and "solve_kernel" in current and int(m.group(1)) != 0:
+            raise RuntimeError(f"{current} uses {m.group(1)} bytes of scratch per lane")
+
+
 def build(verbose: bool = False) -> str:
     """Compile every source (always) and link libibb.so."""
     objs = []
@@ -31,10 +47,15 @@ def build(verbose: bool = False) -> str:
         cmd = [HIPCC, *FLAGS, "-I", INCLUDE, "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd[1:1] = ["-x", "hip"]
+        else:
+            cmd.append("-Rpass-analysis=kernel-resource-usage")
         res = subprocess.run(cmd, capture_output=True, text=True)
-        out = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if "packed-fp32-ops" not in l)
+        text = res.stdout + res.stderr
+        out = "\n".join(l for l in text.splitlines() if "packed-fp32-ops" not in l and "remark:" not in l)
         if res.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{out}")
+        if not src.endswith(".cpp"):
+            check_no_scratch(text)
         if verbose and out.strip():
             print(out, file=sys.stderr)
         objs.append(obj)

@@ -41,3 +41,16 @@ def test_binding_fails_loudly_without_library(tmp_path):
             P.load_library(str(tmp_path / "missing.so"))
     finally:
         P._lib = saved
+
+
+def test_build_rejects_scratch_in_search_kernels():
+    """The build refuses search kernels that spill to scratch memory."""
+    from paper_1802_00330_amd.build import check_no_scratch
+    ok = ("k.hip:1:1: remark: Function Name: _ZN3ibb12solve_kernelILi8ELb0EEEvNS_9SolveArgsE\n"
+          "k.hip:1:1: remark:     ScratchSize [bytes/lane]: 0\n"
+          "k.hip:1:1: remark: Function Name: _ZN3ibb14selftest_kernelEi\n"
+          "k.hip:1:1: remark:     ScratchSize [bytes/lane]: 16\n")
+    check_no_scratch(ok)
+    bad = ok.replace("ScratchSize [bytes/lane]: 0", "ScratchSize [bytes/lane]: 196")
+    with pytest.raises(RuntimeError):
+        check_no_scratch(bad)
