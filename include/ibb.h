@@ -58,6 +58,19 @@ extern "C" {
 #define IBB_SPLIT_WIDEST 0 /* bisect the widest coordinate (first on ties) */
 #define IBB_SPLIT_ALL 1    /* bisect every coordinate: 2^n children (Alg. 2) */
 
+/* Order in which ibb_solve / ibb_solve_async step the boxes of the tree.  The
+ * tree, its counters, the status and the sorted output are the same in both.
+ * IBB_SCHEDULE_QUEUE: a device work queue, each box stepped as soon as it is
+ * created (no wait at the end of a round).  IBB_SCHEDULE_LEVELS: round by
+ * round as in Alg. 1, all boxes of round k before any of round k + 1; with a
+ * budget error the per-level sizes then cover every completed round. */
+#define IBB_SCHEDULE_QUEUE 0
+#define IBB_SCHEDULE_LEVELS 1
+/* IBB_SCHEDULE_AUTO (default): per system shape (n, terms, derivative terms,
+ * split mode) the context times the search kernel once with each schedule,
+ * then keeps the faster one.  Results do not depend on the choice. */
+#define IBB_SCHEDULE_AUTO 2
+
 /* A square polynomial system in sparse monomial form (Sec. 2.1).
  * Equation i owns terms term_off[i] .. term_off[i+1]-1, in the order given;
  * term t is coef[t] * prod_k x_k^expo[t*n + k].  Requirements: 1 <= n <= 16,
@@ -78,6 +91,8 @@ typedef struct {
   int32_t max_recontract;  /* consecutive re-contractions before bisecting (>= 1; 16)   */
   double recontract_ratio; /* re-contract when the width shrank to <= ratio * width (0.5) */
   double hs_max_width;     /* skip the contraction on boxes wider than this (+inf)       */
+  int32_t schedule;        /* IBB_SCHEDULE_AUTO (default), _QUEUE or _LEVELS             */
+  int32_t reserved;        /* must be 0                                                  */
 } ibb_params;
 
 /* Counters of the search tree (identical on every run and on the CPU oracle). */
@@ -197,9 +212,11 @@ int ibb_solve_async(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const
 
 /* Per-level frontier sizes of the most recent ibb_solve on this context
  * (level 0 = the initial box): copies min(count, cap) values, returns the
- * number of levels.  The boxes kept by the exclusion test at a level are the
- * paper's per-round counts (Tables 1, 4, 7) when split_mode = IBB_SPLIT_ALL
- * and the contraction is off (hs_max_width = 0). */
+ * number of levels (boxes at depth k of the tree = the size of round k).  The
+ * boxes kept by the exclusion test at a level are the paper's per-round
+ * counts (Tables 1, 4, 7) when split_mode = IBB_SPLIT_ALL and the
+ * contraction is off (hs_max_width = 0).  After a budget error the sizes are
+ * complete for every finished round with IBB_SCHEDULE_LEVELS only. */
 int64_t ibb_last_level_sizes(ibb_ctx* ctx, int64_t* sizes, int64_t cap);
 
 /* Device time (ms) of the persistent search kernel of the most recent solve

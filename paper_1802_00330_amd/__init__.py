@@ -21,6 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("IBB_LIBRARY") or os.path.join(_HERE, "libibb.so")
 
 OK = 0
+SCHEDULE_QUEUE, SCHEDULE_LEVELS, SCHEDULE_AUTO = 0, 1, 2
 ERR_INVALID_ARG, ERR_BUDGET, ERR_OUTPUT_CAPACITY, ERR_QUEUE_OVERFLOW = -1, -2, -3, -4
 ERR_NO_MEMORY, ERR_DEVICE, ERR_UNSUPPORTED, ERR_TIMEOUT = -5, -6, -7, -8
 SPLIT_WIDEST, SPLIT_ALL = 0, 1
@@ -44,7 +45,7 @@ class IbbSystem(C.Structure):
 class IbbParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_boxes", C.c_int64), ("split_mode", C.c_int32),
                 ("max_recontract", C.c_int32), ("recontract_ratio", C.c_double),
-                ("hs_max_width", C.c_double)]
+                ("hs_max_width", C.c_double), ("schedule", C.c_int32), ("reserved", C.c_int32)]
 
 
 class IbbServerConfig(C.Structure):
@@ -160,9 +161,9 @@ class _SysRef:
 
 def make_params(tol: float, max_boxes: int = 100_000_000, split_mode: int = SPLIT_WIDEST,
                 max_recontract: int = 16, recontract_ratio: float = 0.5,
-                hs_max_width: float = float("inf")) -> IbbParams:
+                hs_max_width: float = float("inf"), schedule: int = 2) -> IbbParams:
     return IbbParams(float(tol), int(max_boxes), int(split_mode), int(max_recontract),
-                     float(recontract_ratio), float(hs_max_width))
+                     float(recontract_ratio), float(hs_max_width), int(schedule), 0)
 
 
 @dataclass

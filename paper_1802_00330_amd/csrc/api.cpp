@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <array>
 #include <map>
+#include <tuple>
 #include <new>
 #include <limits>
 #include <vector>
@@ -33,7 +35,11 @@ hipError_t launch_init(hipStream_t s, Ctrl* c, double* front0, uint32_t* meta0, 
 hipError_t launch_sort(hipStream_t s, const double* box, const uint32_t* tag, const Ctrl* c, int n, int G,
                        long long out_cap, double* out_lo, double* out_hi, uint8_t* out_tag,
                        long long grid_elems);
-hipError_t launch_finalize(hipStream_t s, const Ctrl* c, long long out_cap, long long* info);
+hipError_t launch_finalize(hipStream_t s, const Ctrl* c, long long out_cap, long long* info,
+                           const long long* depth_counts, int level_cap);
+const void* queue_kernel_ptr(int G);
+hipError_t launch_queue_init(hipStream_t s, unsigned long long* seq, long long cap, Ctrl* c, long long* level_sizes,
+                             int level_cap);
 hipError_t launch_selftest(hipStream_t s, int op, long long count, const double* x, const double* y,
                            double* out);
 }  // namespace ibb
@@ -81,6 +87,9 @@ int validate(const ibb_system* s, const double* lo, const double* hi, const ibb_
   if (p->max_recontract < 1) return IBB_ERR_INVALID_ARG;
   if (!(p->recontract_ratio >= 0) || !(p->recontract_ratio <= 1)) return IBB_ERR_INVALID_ARG;
   if (std::isnan(p->hs_max_width)) return IBB_ERR_INVALID_ARG;
+  if (p->schedule != IBB_SCHEDULE_QUEUE && p->schedule != IBB_SCHEDULE_LEVELS && p->schedule != IBB_SCHEDULE_AUTO)
+    return IBB_ERR_INVALID_ARG;
+  if (p->reserved != 0) return IBB_ERR_INVALID_ARG;
   if (T > IBB_MAX_TERMS) return IBB_ERR_UNSUPPORTED;
   if (p->max_recontract > 255) return IBB_ERR_UNSUPPORTED;
   return IBB_OK;
@@ -173,7 +182,7 @@ void compile(const ibb_system* s, Compiled& c) {
 
 // Device workspace partition of one solve.
 struct WsLayout {
-  size_t ctrl, level, blob, box, front0, front1, meta0, meta1, out_box, out_tag, total;
+  size_t ctrl, level, blob, box, front0, front1, meta0, meta1, out_box, out_tag, seq, total;
 };
 
 WsLayout ws_layout(int n, size_t blob_words, long long frontier_cap, long long out_cap) {
@@ -195,8 +204,17 @@ WsLayout ws_layout(int n, size_t blob_words, long long frontier_cap, long long o
   L.meta1 = take(sizeof(uint32_t) * (size_t)frontier_cap);
   L.out_box = take(sizeof(double) * 2 * G * (size_t)out_cap);
   L.out_tag = take(sizeof(uint32_t) * (size_t)out_cap);
+  L.seq = take(sizeof(unsigned long long) * (size_t)frontier_cap);
   L.total = o;
   return L;
+}
+
+// Ring capacity of a work-queue search: the largest power of two that fits
+// the level-0 frontier buffer.
+long long ring_capacity(long long frontier_cap) {
+  long long c = 1;
+  while (c * 2 <= frontier_cap) c *= 2;
+  return c;
 }
 
 // Upper bound of the system blob size for a given n (IBB_MAX_TERMS terms).
@@ -215,6 +233,7 @@ struct ibb_ctx {
   long long clock_khz = 100000;
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, staged = nullptr;
+  hipEvent_t done = nullptr;  // end of the last single-system solve (after its d_info)
   bool staged_pending = false;
   bool timed_pending = false;  // ev0/ev1 bracket the last persistent launch
   void* ws = nullptr;  // workspace of the host-pointer entry points
@@ -227,6 +246,13 @@ struct ibb_ctx {
   std::vector<long long> last_levels;
   void* bws = nullptr;  // batch workspace
   size_t bws_bytes = 0;
+  // schedule autotuner: best kernel time per (n, T, TD, split mode) and
+  // schedule, and the shape / schedule of the launch ev0..ev1 last bracketed
+  std::map<std::tuple<int, int, int, int>, std::array<float, 2>> tune;
+  bool tune_pending = false;
+  std::tuple<int, int, int, int> tune_key;
+  int tune_sched = 0;
+  const long long* tune_info = nullptr;  // d_info of that launch (its status)
 };
 
 namespace {
@@ -315,7 +341,7 @@ int persistent_geometry(ibb_ctx* ctx, const void* fn, size_t table_bytes, int G,
 // whose control block and level-0 frontier are already in place.
 int launch_search(ibb_ctx* ctx, const Compiled& c, const ibb_params* p, char* ws, const WsLayout& L,
                   long long frontier_cap, long long out_cap, long long max_boxes, hipStream_t s, int max_levels,
-                  double* d_dbg) {
+                  double* d_dbg, bool queue = false) {
   const int n = c.n, G = c.G;
   Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
   SolveArgs a;
@@ -343,8 +369,12 @@ int launch_search(ibb_ctx* ctx, const Compiled& c, const ibb_params* p, char* ws
   a.dbg = d_dbg;
   a.out_count = &ctrl->out_count;
   a.out_stride = G;
+  if (queue) {
+    a.front_cap = ring_capacity(frontier_cap);
+    a.qseq = reinterpret_cast<unsigned long long*>(ws + L.seq);
+  }
 
-  const void* fn = solve_kernel_ptr(G, false);
+  const void* fn = queue ? queue_kernel_ptr(G) : solve_kernel_ptr(G, false);
   const size_t tbytes = (table_lds_bytes(n, c.T, c.TD) + 15) & ~size_t(15);
   Geometry geo;
   {
@@ -354,6 +384,7 @@ int launch_search(ibb_ctx* ctx, const Compiled& c, const ibb_params* p, char* ws
   a.nblocks = geo.blocks;
   a.jrs = geo.jrs;
   void* args[] = {&a};
+  ctx->tune_pending = false;  // ev0 / ev1 now bracket this launch
   hipEventRecord(ctx->ev0, s);
   if (hipLaunchCooperativeKernel(fn, dim3(geo.blocks), dim3(64 * geo.waves), args, (unsigned)geo.lds, s) !=
       hipSuccess)
@@ -361,6 +392,43 @@ int launch_search(ibb_ctx* ctx, const Compiled& c, const ibb_params* p, char* ws
   hipEventRecord(ctx->ev1, s);
   ctx->timed_pending = true;
   return IBB_OK;
+}
+
+// Schedule of a full solve.  With IBB_SCHEDULE_AUTO, the kernel time of the
+// previous single-system launch is first credited to its shape and schedule;
+// a shape still missing a measurement gets the schedule it lacks.
+int resolve_schedule(ibb_ctx* ctx, const Compiled& c, const ibb_params* p) {
+  if (ctx->tune_pending) {
+    auto it = ctx->tune.find(ctx->tune_key);
+    const bool learning = it != ctx->tune.end() && (it->second[0] < 0 || it->second[1] < 0);
+    long long status = 0;
+    if (learning) {
+      hipEventSynchronize(ctx->done);
+      // a launch that stopped early (capacity, budget) says nothing about speed
+      if (ctx->tune_info) hipMemcpy(&status, ctx->tune_info, sizeof status, hipMemcpyDeviceToHost);
+    }
+    if (status == 0 && hipEventQuery(ctx->ev1) == hipSuccess) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) == hipSuccess && it != ctx->tune.end()) {
+        float& slot = it->second[ctx->tune_sched];
+        slot = slot < 0 ? ms : std::min(slot, ms);
+      }
+    }
+    ctx->tune_pending = false;
+  }
+  const auto key = std::make_tuple(c.n, c.T, c.TD, p->split_mode);
+  auto it = ctx->tune.find(key);
+  if (it == ctx->tune.end()) it = ctx->tune.emplace(key, std::array<float, 2>{-1.0f, -1.0f}).first;
+  int sched = p->schedule;
+  if (sched == IBB_SCHEDULE_AUTO) {
+    if (it->second[0] < 0) sched = IBB_SCHEDULE_QUEUE;
+    else if (it->second[1] < 0) sched = IBB_SCHEDULE_LEVELS;
+    else sched = it->second[1] < it->second[0] ? IBB_SCHEDULE_LEVELS : IBB_SCHEDULE_QUEUE;
+  }
+  // credited when the next solve is enqueued (see above)
+  ctx->tune_key = key;
+  ctx->tune_sched = sched;
+  return sched;
 }
 
 // Enqueue one solve into a partitioned workspace; outputs to device arrays.
@@ -391,14 +459,26 @@ int enqueue_solve(ibb_ctx* ctx, const Compiled& c, const double* lo, const doubl
                   dlo, dlo + kMaxN, n, G) != hipSuccess)
     return IBB_ERR_DEVICE;
 
+  // full solves run as a work queue; single levels (diagnostics) level by level
+  const bool full_solve = max_levels == 0 && d_dbg == nullptr;
+  const bool queue = full_solve && resolve_schedule(ctx, c, p) == IBB_SCHEDULE_QUEUE;
+  long long* depth_counts = reinterpret_cast<long long*>(ws + L.level);
+  if (queue && launch_queue_init(s, reinterpret_cast<unsigned long long*>(ws + L.seq), ring_capacity(frontier_cap),
+                                 ctrl, depth_counts, kLevelCap) != hipSuccess)
+    return IBB_ERR_DEVICE;
   {
-    const int lst = launch_search(ctx, c, p, ws, L, frontier_cap, out_cap, p->max_boxes, s, max_levels, d_dbg);
+    const int lst =
+        launch_search(ctx, c, p, ws, L, frontier_cap, out_cap, p->max_boxes, s, max_levels, d_dbg, queue);
     if (lst) return lst;
+    ctx->tune_pending = full_solve;
+    ctx->tune_info = d_info;
   }
   if (launch_sort(s, reinterpret_cast<const double*>(ws + L.out_box), reinterpret_cast<const uint32_t*>(ws + L.out_tag),
                   ctrl, n, G, out_cap, d_out_lo, d_out_hi, d_out_tag, out_cap) != hipSuccess)
     return IBB_ERR_DEVICE;
-  if (launch_finalize(s, ctrl, out_cap, d_info) != hipSuccess) return IBB_ERR_DEVICE;
+  if (launch_finalize(s, ctrl, out_cap, d_info, queue ? depth_counts : nullptr, kLevelCap) != hipSuccess)
+    return IBB_ERR_DEVICE;
+  hipEventRecord(ctx->done, s);
   return IBB_OK;
 }
 
@@ -553,6 +633,7 @@ extern "C" int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* system
     if (launch_prep(s, reinterpret_cast<uint64_t*>(D(L.blobs)), reinterpret_cast<const long long*>(D(L.boff)),
                     B) != hipSuccess)
       return IBB_ERR_DEVICE;
+    ctx->tune_pending = false;
     hipEventRecord(ctx->ev0, s);
     for (int q = 0; q < 4; ++q) {
       const int m = bucket_start[q + 1] - bucket_start[q];
@@ -704,6 +785,8 @@ void ibb_params_default(ibb_params* p) {
   p->max_recontract = 16;
   p->recontract_ratio = 0.5;
   p->hs_max_width = INFINITY;
+  p->schedule = IBB_SCHEDULE_AUTO;
+  p->reserved = 0;
 }
 
 int ibb_ctx_create(int device, ibb_ctx** out) {
@@ -729,6 +812,7 @@ int ibb_ctx_create(int device, ibb_ctx** out) {
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
       hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&c->info), sizeof(long long) * kInfoLen) != hipSuccess) {
     ibb_ctx_destroy(c);
     return IBB_ERR_DEVICE;
@@ -749,6 +833,7 @@ void ibb_ctx_destroy(ibb_ctx* c) {
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
   if (c->staged) hipEventDestroy(c->staged);
+  if (c->done) hipEventDestroy(c->done);
   if (c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1334,6 +1419,7 @@ int ibb_server_step(ibb_server* sv) {
   if (!admitted.empty() && launch_prep(s, sv->blobs, sv->boff, S) != hipSuccess) return IBB_ERR_DEVICE;
   // ---- one quantum of levels per bucket
   bool any = false;
+  ctx->tune_pending = false;
   hipEventRecord(ctx->ev0, s);
   for (int q = 0; q < 4; ++q) {
     Bucket& b = sv->bk[q];

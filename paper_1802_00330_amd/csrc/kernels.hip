@@ -313,16 +313,50 @@ __device__ __forceinline__ void sys_add(unsigned long long* arr, uint32_t sysid,
   }
 }
 
-template <int G, bool MULTI>
+// Work-queue mode: waits (bounded) until ring slot `at` is free for item t.
+// A ring that stays full means the live boxes outgrew it: the search stops
+// with IBB_ERR_QUEUE_OVERFLOW and the host retries with a larger ring.
+__device__ __forceinline__ bool ring_slot_free(const SolveArgs& a, unsigned long long t, size_t at) {
+  if (__hip_atomic_load(&a.qseq[at], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == t) return true;
+  const long long t0 = wall_clock64();
+  for (;;) {
+    __builtin_amdgcn_s_sleep(2);
+    if (__hip_atomic_load(&a.qseq[at], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == t) return true;
+    if (__hip_atomic_load(&a.ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    if (wall_clock64() - t0 > a.timeout_ticks / 64) {
+      atomicCAS(&a.ctrl->status, 0, -4);
+      return false;
+    }
+  }
+}
+
+// Per-wave state of a work-queue search, kept in registers: the deepest level
+// seen, a run of boxes of one depth not yet added to the depth counts, and the
+// wave's share of `pending` not yet applied (never positive, so the global
+// count never falls below the boxes still to step).
+struct QueueLocal {
+  unsigned depth_max = 0;
+  unsigned run_depth = 0;
+  unsigned long long run_count = 0;
+  long long pend = 0;
+};
+
+// Level mode (QUEUE = false): boxes [base, base + W) of level `level` in
+// front[cur], children appended to front[cur ^ 1].  Work-queue mode: each
+// group's box is in ring slot qslot (valid when qvalid), children are
+// reserved at the ring's tail and published through qseq.
+template <int G, bool MULTI, bool QUEUE = false>
 __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, Scratch<G>& S, const JView J,
                           long long base,
                           long long cnt, int cur, int level, unsigned long long* next_count,
-                          StepCounters& sc) {
+                          StepCounters& sc, long long qslot = 0, bool qvalid = false,
+                          QueueLocal* ql = nullptr) {
   const int lane = __lane_id();
   const int g = lane / G;
   const int r = lane % G;
-  const long long idx = base + g;
-  bool valid = idx < cnt;
+  const unsigned long long qmask = (unsigned long long)a.front_cap - 1ull;
+  const long long idx = QUEUE ? qslot : base + g;
+  bool valid = QUEUE ? qvalid : idx < cnt;
   // the group's system: its table, size and parameters
   LTable T = Tl;
   uint32_t sysid = 0;
@@ -357,15 +391,52 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
   // ---- load the box and its record
   uint32_t meta = 0;
   if (valid) {
+    const size_t at = QUEUE ? (size_t)((unsigned long long)idx & qmask) : (size_t)idx;
+    const int buf = QUEUE ? 0 : cur;
     if (row_ok) {
-      const double* src = a.front[cur] + ((size_t)idx * G + r) * 2;
+      const double* src = a.front[buf] + (at * G + r) * 2;
       S.X[g][r] = iv{src[0], src[1]};
     }
-    meta = a.meta[cur][idx];
+    meta = a.meta[buf][at];
   }
   const bool proven = meta & 1u;
   const int rc = (int)((meta >> 8) & 0xFF);
   wave_lds_sync();
+  if (QUEUE) {
+    // the slot is read (the loads above are complete once this wave's release
+    // fence returns): free it for the item one ring length later
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (valid && r == 0)
+      __hip_atomic_store(&a.qseq[(unsigned long long)idx & qmask], (unsigned long long)idx + qmask + 1ull,
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // boxes per depth (the round sizes of Alg. 1): runs of one depth are
+    // counted in registers and added when the depth changes
+    const unsigned depth = meta >> 16;
+    const bool lead = valid && r == 0;
+    const uint64_t vm = __ballot(lead);
+    if (vm) {
+      const unsigned d0 = __shfl(depth, __ffsll((long long)vm) - 1, 64);
+      const bool same = __ballot(lead && depth == d0) == vm;
+      const unsigned long long nv = (unsigned long long)__popcll(vm);
+      if (same && (d0 == ql->run_depth || ql->run_count == 0)) {
+        ql->run_depth = d0;
+        ql->run_count += nv;
+      } else if (same) {
+        if (lane == 0 && ql->run_depth < (unsigned)a.level_cap)
+          atomicAdd(reinterpret_cast<unsigned long long*>(&a.level_sizes[ql->run_depth]), ql->run_count);
+        ql->run_depth = d0;
+        ql->run_count = nv;
+      } else if (lead && depth < (unsigned)a.level_cap) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(&a.level_sizes[depth]), 1ull);
+      }
+      if (d0 + 1 > ql->depth_max) ql->depth_max = d0 + 1;
+      if (!same) {
+        unsigned dm = lead ? depth + 1 : 0u;
+        for (int o = 32; o > 0; o >>= 1) dm = max(dm, (unsigned)__shfl_xor((int)dm, o, 64));
+        if (dm > ql->depth_max) ql->depth_max = dm;
+      }
+    }
+  }
 
   // ---- exclusion test (Def. 2): some F_i(X) excludes 0
   bool excl_row = false;
@@ -633,6 +704,7 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
   int kk = r, whok = r;
   group_argmax<G>(wn, kk, whok);
 
+  const uint32_t child_depth = QUEUE ? ((meta >> 16) + 1u) << 16 : 0u;
   int n_push = 0;
   bool emit = false;
   int tag = 0;
@@ -648,7 +720,7 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
       if (wn < w && rc + 1 < p_maxrc) {
         kind = 1;
         n_push = 1;
-        child_meta = 1u | ((uint32_t)(rc + 1) << 8);
+        child_meta = 1u | ((uint32_t)(rc + 1) << 8) | child_depth;
       } else {
         emit = true;
         tag = 1;
@@ -656,7 +728,7 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
     } else if (wn <= rmul(p_ratio, w) && rc + 1 < p_maxrc) {
       kind = 1;
       n_push = 1;
-      child_meta = (uint32_t)(rc + 1) << 8;
+      child_meta = ((uint32_t)(rc + 1) << 8) | child_depth;
     } else if (p_split == 0) {
       const iv xk = S.Xn[g][kk];
       mid_kk = imid(xk);
@@ -727,7 +799,12 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
   const unsigned tot_e = __shfl(incl_e, 63, 64);
   unsigned long long pbase = 0, ebase = 0;
   if (lane == 0) {
-    if (tot_p) pbase = atomicAdd(next_count, (unsigned long long)tot_p);
+    if (tot_p) {
+      pbase = atomicAdd(QUEUE ? &a.ctrl->qtail : next_count, (unsigned long long)tot_p);
+      // work queue: every created box is a tree node, so the budget (more
+      // than max_boxes nodes) fails exactly when the boxes created exceed it
+      if (QUEUE && pbase + tot_p > (unsigned long long)a.max_boxes) atomicCAS(&a.ctrl->status, 0, -2);
+    }
     if (tot_e && !(MULTI && a.slot_out_cap > 0)) ebase = atomicAdd(a.out_count, (unsigned long long)tot_e);
   }
   pbase = __shfl(pbase, 0, 64);
@@ -735,7 +812,6 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
   const unsigned gp = __shfl(incl_p - my_push, g * G, 64);
   const unsigned ge = __shfl(incl_e - my_emit, g * G, 64);
 
-  const int nxt = cur ^ 1;
   unsigned long long slot_o = 0;
   if (MULTI && a.slot_out_cap > 0) {
     // per-system output regions (serving): one record per emitted box
@@ -769,56 +845,55 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
       }
     }
   }
+  // children: level mode appends to the next level's buffer; work-queue mode
+  // writes into the reserved ring items once their slots are free
+  const unsigned long long o = pbase + gp;
+  int pushed = 0;
   if (n_push) {
-    const unsigned long long o = pbase + gp;
     const iv x = row_ok ? S.Xn[g][r] : iv{0.0, 0.0};
-    if (kind == 1) {
-      if (o < (unsigned long long)a.front_cap) {
-        if (row_ok) {
-          double* dst = a.front[nxt] + ((size_t)o * G + r) * 2;
-          dst[0] = x.lo;
-          dst[1] = x.nhi;
-        }
-        if (r == 0) {
-          a.meta[nxt][o] = child_meta;
-          if (MULTI) a.sys[nxt][o] = sysid;
-        }
+    const bool mine = (split_mask >> r) & 1u;
+    const int q = __popc(split_mask & ((1u << r) - 1u));
+    const double m = (kind == 3 && row_ok) ? imid(x) : 0.0;
+    const int buf = QUEUE ? 0 : cur ^ 1;
+    for (int c = 0; c < n_push; ++c) {
+      const unsigned long long t = o + (unsigned long long)c;
+      size_t at;
+      if (QUEUE) {
+        at = (size_t)(t & qmask);
+        if (!ring_slot_free(a, t, at)) break;
+      } else {
+        if (t >= (unsigned long long)a.front_cap) break;
+        at = (size_t)t;
       }
-    } else if (kind == 2) {
-      for (int c = 0; c < 2; ++c) {
-        if (o + c < (unsigned long long)a.front_cap) {
-          if (row_ok) {
-            iv y = x;
-            if (r == kk) y = c ? iv{mid_kk, x.nhi} : iv{x.lo, -mid_kk};
-            double* dst = a.front[nxt] + ((size_t)(o + c) * G + r) * 2;
-            dst[0] = y.lo;
-            dst[1] = y.nhi;
-          }
-          if (r == 0) {
-            a.meta[nxt][o + c] = 0u;
-            if (MULTI) a.sys[nxt][o + c] = sysid;
-          }
-        }
+      if (row_ok) {
+        iv y = x;
+        if (kind == 2 && r == kk) y = c ? iv{mid_kk, x.nhi} : iv{x.lo, -mid_kk};
+        if (kind == 3 && mine) y = ((c >> q) & 1) ? iv{m, x.nhi} : iv{x.lo, -m};
+        double* dst = a.front[buf] + (at * G + r) * 2;
+        dst[0] = y.lo;
+        dst[1] = y.nhi;
       }
-    } else {
-      const bool mine = (split_mask >> r) & 1u;
-      const int q = __popc(split_mask & ((1u << r) - 1u));
-      const double m = row_ok ? imid(x) : 0.0;
-      for (int c = 0; c < n_push; ++c) {
-        if (o + c < (unsigned long long)a.front_cap) {
-          if (row_ok) {
-            iv y = x;
-            if (mine) y = ((c >> q) & 1) ? iv{m, x.nhi} : iv{x.lo, -m};
-            double* dst = a.front[nxt] + ((size_t)(o + c) * G + r) * 2;
-            dst[0] = y.lo;
-            dst[1] = y.nhi;
-          }
-          if (r == 0) {
-            a.meta[nxt][o + c] = 0u;
-            if (MULTI) a.sys[nxt][o + c] = sysid;
-          }
-        }
+      if (r == 0) {
+        a.meta[buf][at] = kind == 1 ? child_meta : child_depth;
+        if (MULTI) a.sys[buf][at] = sysid;
       }
+      pushed = c + 1;
+    }
+  }
+  if (QUEUE) {
+    // publish: the box stores above become visible before the slot flags
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (r == 0)
+      for (int c = 0; c < pushed; ++c)
+        __hip_atomic_store(&a.qseq[(o + (unsigned long long)c) & qmask], o + (unsigned long long)c + 1ull,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // boxes still to step: + children - this box, summed over the wave; a
+    // positive balance is applied at once (after the children are published)
+    const unsigned delta = (valid && r == 0) ? (unsigned)(n_push - 1) : 0u;
+    ql->pend += (long long)(int)__shfl(wave_inclusive_sum(delta), 63, 64);
+    if (ql->pend > 0) {
+      if (lane == 0) atomicAdd(&a.ctrl->pending, (unsigned long long)ql->pend);
+      ql->pend = 0;
     }
   }
   wave_lds_sync();
@@ -926,6 +1001,116 @@ solve_kernel(SolveArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Work-queue search of one system.  The boxes of the tree live in a ring of
+// front_cap slots (front[0], meta[0]); every group of G lanes holds one claimed
+// ring item, waits until the item's box has been published, and the wave
+// steps the groups whose boxes are there.  Nothing waits for a level to end:
+// the search tree, its counters and the sorted output are those of the level
+// by level search (a box's children depend on the box alone), and the boxes
+// per depth are the round sizes.  pending counts boxes created and not yet
+// stepped; it reaches zero exactly when the search is over.  Every wait is
+// bounded (IBB_ERR_TIMEOUT, IBB_ERR_QUEUE_OVERFLOW).
+// ---------------------------------------------------------------------------
+template <int G>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Occupancy<G, false>::waves)))
+queue_kernel(SolveArgs a) {
+  set_fp64_round_down();
+  extern __shared__ __align__(16) char smem[];
+  const SysDesc* d = reinterpret_cast<const SysDesc*>(a.blob);
+  const LTable T = stage_table(a.blob, smem);
+  const size_t table_bytes = align16(table_lds_bytes(d->n, d->T, d->TD));
+  const int jn = d->n;
+  char* const wave_base = smem + table_bytes + (threadIdx.x / 64) * wave_scratch_bytes<G>(jn, a.jrs);
+  Scratch<G>* S = reinterpret_cast<Scratch<G>*>(wave_base);
+  const JView J{reinterpret_cast<iv*>(wave_base + ((sizeof(Scratch<G>) + 15) / 16) * 16), jn * a.jrs + 1, a.jrs};
+  __syncthreads();
+
+  StepCounters sc;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) sc.s[i] = 0;
+  const int lane = __lane_id();
+  const int g = lane / G;
+  const int r = lane % G;
+  Ctrl* c = a.ctrl;
+  const unsigned long long qmask = (unsigned long long)a.front_cap - 1ull;
+  long long slot = -1;  // this group's ring item (uniform over the group)
+  QueueLocal ql;
+  for (;;) {
+    // groups without an item claim the next ones, one atomic per wave
+    const uint64_t needm = __ballot(slot < 0 && r == 0);
+    unsigned long long base = 0;
+    if (lane == 0 && needm) base = atomicAdd(&c->qhead, (unsigned long long)__popcll(needm));
+    base = __shfl(base, 0, 64);
+    if (slot < 0) {
+      const uint64_t below = (g == 0) ? 0ull : (needm & ((1ull << (g * G)) - 1ull));
+      slot = (long long)(base + (unsigned long long)__popcll(below));
+    }
+    // wait until some group's box is published, or the search is over
+    bool full = false;
+    bool stop = false;
+    const long long t0 = wall_clock64();
+    for (;;) {
+      unsigned long long v = 0;
+      if (r == 0) v = __hip_atomic_load(&a.qseq[(unsigned long long)slot & qmask], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+      full = __shfl(v, g * G, 64) == (unsigned long long)slot + 1ull;
+      if (__ballot(full) != 0) break;
+      int st = 0;
+      unsigned long long pend = 1;
+      if (lane == 0) {
+        st = __hip_atomic_load(&c->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        pend = __hip_atomic_load(&c->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (st == 0 && pend != 0 && wall_clock64() - t0 > a.timeout_ticks) {
+          atomicCAS(&c->status, 0, -8);
+          st = -8;
+        }
+      }
+      st = __shfl(st, 0, 64);
+      pend = __shfl(pend, 0, 64);
+      if (ql.pend != 0) {
+        // idle: apply the wave's share first (the global count can reach
+        // zero only once every wave has applied its share)
+        if (lane == 0) atomicAdd(&c->pending, (unsigned long long)ql.pend);
+        ql.pend = 0;
+        continue;
+      }
+      if (st != 0 || pend == 0) {
+        stop = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (stop) break;
+    // the published boxes are read after this point
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    step_tile<G, false, true>(a, T, *S, J, 0, 0, 0, 0, nullptr, sc, slot, full, &ql);
+    if (full) slot = -1;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (sc.s[i]) atomicAdd(&c->stats[i], sc.s[i]);
+    if (ql.run_count && ql.run_depth < (unsigned)a.level_cap)
+      atomicAdd(reinterpret_cast<unsigned long long*>(&a.level_sizes[ql.run_depth]), ql.run_count);
+    if (ql.depth_max) atomicMax(&c->levels, (unsigned long long)ql.depth_max);
+  }
+}
+
+// Ring of a work-queue search: every slot free for its first item, except
+// slot 0, which holds the initial box (written by init_kernel); no box stepped.
+__global__ void queue_init_kernel(unsigned long long* seq, long long cap, Ctrl* c, long long* level_sizes,
+                                  int level_cap) {
+  const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = i0; i < cap; i += stride) seq[i] = (i == 0) ? 1ull : (unsigned long long)i;
+  for (long long i = i0; i < level_cap; i += stride) level_sizes[i] = 0;
+  if (i0 == 0) {
+    c->qtail = 1ull;
+    c->pending = 1ull;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Output: canonical (-0 -> +0) boxes sorted lexicographically by
 // (lo_0..lo_{n-1}, hi_0..hi_{n-1}, tag).  Each element finds its rank by
 // comparing with all others (ties broken by the original index).
@@ -968,7 +1153,9 @@ __global__ void sort_kernel(const double* box, const uint32_t* tag, const Ctrl* 
 }
 
 // d_info: status, box count, the eight tree counters, levels, widest level.
-__global__ void finalize_kernel(const Ctrl* c, long long out_cap, long long* info) {
+// With depth counts (work-queue search) the widest level is their maximum.
+__global__ void finalize_kernel(const Ctrl* c, long long out_cap, long long* info, const long long* depth_counts,
+                                int level_cap) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int st = c->status;
   if (st == 0 && c->out_count > (unsigned long long)out_cap) st = -3;
@@ -976,7 +1163,12 @@ __global__ void finalize_kernel(const Ctrl* c, long long out_cap, long long* inf
   info[1] = (long long)c->out_count;
   for (int i = 0; i < 8; ++i) info[2 + i] = (long long)c->stats[i];
   info[10] = (long long)c->levels;
-  info[11] = (long long)c->max_frontier;
+  long long widest = (long long)c->max_frontier;
+  if (depth_counts) {
+    const long long m = (long long)c->levels < level_cap ? (long long)c->levels : level_cap;
+    for (long long i = 0; i < m; ++i) widest = depth_counts[i] > widest ? depth_counts[i] : widest;
+  }
+  info[11] = widest;
 }
 
 // Initial state of a solve: control block, the root box at level 0.
@@ -1154,8 +1346,26 @@ hipError_t launch_sort(hipStream_t s, const double* box, const uint32_t* tag, co
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(hipStream_t s, const Ctrl* c, long long out_cap, long long* info) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, s, c, out_cap, info);
+hipError_t launch_finalize(hipStream_t s, const Ctrl* c, long long out_cap, long long* info,
+                           const long long* depth_counts, int level_cap) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, s, c, out_cap, info, depth_counts, level_cap);
+  return hipGetLastError();
+}
+
+const void* queue_kernel_ptr(int G) {
+  switch (G) {
+    case 2: return reinterpret_cast<const void*>(&queue_kernel<2>);
+    case 4: return reinterpret_cast<const void*>(&queue_kernel<4>);
+    case 8: return reinterpret_cast<const void*>(&queue_kernel<8>);
+    default: return reinterpret_cast<const void*>(&queue_kernel<16>);
+  }
+}
+
+hipError_t launch_queue_init(hipStream_t s, unsigned long long* seq, long long cap, Ctrl* c, long long* level_sizes,
+                             int level_cap) {
+  const long long work = cap > level_cap ? cap : level_cap;
+  const int blocks = (int)std::min<long long>((work + 255) / 256, 4096);
+  hipLaunchKernelGGL(queue_init_kernel, dim3(blocks), dim3(256), 0, s, seq, cap, c, level_sizes, level_cap);
   return hipGetLastError();
 }
 

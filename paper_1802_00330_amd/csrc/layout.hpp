@@ -41,6 +41,9 @@ struct Ctrl {
                                  // recontracted, bisected, emitted_unique, emitted_undecided
   unsigned long long levels;
   unsigned long long max_frontier;
+  // work-queue search (one system): monotone claim and reservation counters of
+  // the ring (qtail = boxes created, the budget), boxes created and not yet stepped
+  unsigned long long qhead, qtail, pending, qspare;
   int32_t status;
   int32_t pad[7];
 };
@@ -55,7 +58,8 @@ struct SysParams {
 struct SolveArgs {
   const uint64_t* blob;
   double* front[2];  // boxes as (lo, -hi) pairs, [cap][G][2]
-  uint32_t* meta[2]; // bit 0 proven, bits 8..15 consecutive re-contractions
+  uint32_t* meta[2]; // bit 0 proven, bits 8..15 consecutive re-contractions,
+                     // bits 16..31 depth in the tree (work-queue search)
   long long front_cap;
   double* out_box;   // [out_cap][G][2]
   uint32_t* out_tag;
@@ -85,6 +89,9 @@ struct SolveArgs {
   int out_stride;  // coordinates per output record (G for one system, kMaxN for batches)
   int level0;      // index of the first level of this launch (continuing searches)
   int jrs;         // row stride (in intervals) of the per-box Jacobian in LDS
+  // work-queue search: front[0]/meta[0] form a ring of front_cap (a power of
+  // two) slots; qseq[s] = t: slot free for item t, t + 1: slot holds item t
+  unsigned long long* qseq;
   int slot_out_cap;  // > 0: each system emits into its own region of this many boxes
   unsigned long long* slot_out_count;  // [B] boxes emitted per system (regions)
   unsigned long long* pending_sys;     // [B] boxes per system still to step (or null)

@@ -33,7 +33,8 @@ def test_paper_round_counts_on_gpu(gpu_ctx, name):
     if budget is None:
         pytest.skip("round-2 count unknown")
     print(f"[paper-rounds] {name} budget={budget}", flush=True)
-    r = P.ibb_solve(gpu_ctx, s, P.make_params(1e-6, max_boxes=budget, split_mode=P.SPLIT_ALL, hs_max_width=0.0))
+    r = P.ibb_solve(gpu_ctx, s, P.make_params(1e-6, max_boxes=budget, split_mode=P.SPLIT_ALL, hs_max_width=0.0,
+                                                schedule=P.SCHEDULE_LEVELS))
     assert r.status == P.ERR_BUDGET
     sizes = P.ibb_last_level_sizes(gpu_ctx)
     assert len(sizes) == 5 and sizes[0] == 1
