@@ -192,8 +192,11 @@ int ibb_server_cancel(ibb_server* server, int64_t id);
 int ibb_server_pending(ibb_server* server, int64_t* queued, int64_t* active);
 
 /* Device workspace (bytes) that ibb_solve_async needs for a system with n
- * variables, a frontier of `frontier_cap` boxes per tree level and `out_cap`
- * output boxes. */
+ * variables, a frontier of `frontier_cap` boxes and `out_cap` output boxes.
+ * The level-by-level schedule holds one tree level (at most frontier_cap
+ * boxes) at a time; the work-queue schedule keeps the boxes created and not
+ * yet stepped in a ring of the largest power of two <= frontier_cap slots.
+ * Either overflow ends the solve with IBB_ERR_QUEUE_OVERFLOW. */
 size_t ibb_workspace_size(int32_t n, int64_t frontier_cap, int64_t out_cap);
 
 /* Enqueue a solve on `stream` (a hipStream_t, NULL = default stream) using
@@ -204,7 +207,9 @@ size_t ibb_workspace_size(int32_t n, int64_t frontier_cap, int64_t out_cap);
  *   status is IBB_ERR_OUTPUT_CAPACITY), [2..11] the ibb_stats counters in
  *   order (processed .. max_frontier).
  * The host inputs are copied before the call returns.  Returns IBB_OK when the
- * work was enqueued; argument errors are returned directly. */
+ * work was enqueued; argument errors are returned directly.  With
+ * IBB_SCHEDULE_AUTO, while a system shape is still being timed, the call
+ * waits for the previous solve enqueued on this context to finish. */
 int ibb_solve_async(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const double* hi,
                     const ibb_params* params, void* d_ws, size_t ws_bytes, int64_t frontier_cap,
                     int64_t out_cap, double* d_out_lo, double* d_out_hi, uint8_t* d_out_tag,
