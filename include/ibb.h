@@ -151,6 +151,23 @@ int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const do
                     uint8_t* out_tag, int64_t cap, int64_t* out_off, int32_t* status,
                     ibb_stats* stats);
 
+/* A batch prepared once and solved repeatedly (same members, same boxes):
+ * ibb_batch_plan_create validates and compiles the members, uploads them into
+ * device memory owned by the plan and records the device work of a batch solve
+ * (counter resets by fill kernels, initial boxes, one persistent launch per
+ * lane-count bucket) into a HIP graph; ibb_batch_plan_run replays the graph on
+ * the plan's stream and returns results exactly as ibb_solve_batch (same
+ * arguments and meaning).  A frontier or output overflow re-records the graph
+ * with larger capacities.  IBB_ERR_UNSUPPORTED if the runtime cannot record
+ * the launches.  The systems and boxes are copied at creation; one plan runs
+ * one batch at a time. */
+typedef struct ibb_batch_plan ibb_batch_plan;
+int ibb_batch_plan_create(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const double* lo,
+                          const double* hi, const ibb_params* params, ibb_batch_plan** plan);
+int ibb_batch_plan_run(ibb_batch_plan* plan, double* out_lo, double* out_hi, uint8_t* out_tag,
+                       int64_t cap, int64_t* out_off, int32_t* status, ibb_stats* stats);
+void ibb_batch_plan_destroy(ibb_batch_plan* plan);
+
 /* ---- serving: continuous batching of solves on one device ----
  * Requests are queued by ibb_server_submit (the system is copied).  Each call
  * of ibb_server_step (1) admits queued requests while a device slot is free

@@ -35,7 +35,8 @@ EXPORTS = ("ibb_ctx_create", "ibb_ctx_destroy", "ibb_strerror", "ibb_params_defa
            "ibb_workspace_size", "ibb_solve_async", "ibb_last_level_sizes", "ibb_last_kernel_ms",
            "ibb_selftest_ops", "ibb_debug_step", "ibb_solve_batch", "ibb_server_config_default",
            "ibb_server_create", "ibb_server_destroy", "ibb_server_submit", "ibb_server_step", "ibb_server_poll",
-           "ibb_server_cancel", "ibb_server_pending", "ibb_round")
+           "ibb_server_cancel", "ibb_server_pending", "ibb_round", "ibb_batch_plan_create", "ibb_batch_plan_run",
+           "ibb_batch_plan_destroy")
 
 
 class IbbSystem(C.Structure):
@@ -106,6 +107,11 @@ def load_library(path: str = LIB_PATH):
     L.ibb_server_pending.argtypes = [p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.ibb_debug_step.restype = C.c_int
     L.ibb_debug_step.argtypes = [p, C.POINTER(IbbSystem), p, p, C.POINTER(IbbParams), p, i64]
+    L.ibb_batch_plan_create.restype = C.c_int
+    L.ibb_batch_plan_create.argtypes = [p, i32, p, p, p, p, C.POINTER(C.c_void_p)]
+    L.ibb_batch_plan_run.restype = C.c_int
+    L.ibb_batch_plan_run.argtypes = [p, p, p, p, i64, p, p, p]
+    L.ibb_batch_plan_destroy.restype, L.ibb_batch_plan_destroy.argtypes = None, [p]
     L.ibb_round.restype = C.c_int
     L.ibb_round.argtypes = [p, C.POINTER(IbbSystem), C.POINTER(IbbParams), i64, p, p, p, p, p, p, i64,
                             C.POINTER(C.c_int64), p, p, p, i64, C.POINTER(C.c_int64), C.POINTER(IbbStats)]
@@ -346,9 +352,7 @@ def ibb_round(ctx: Context, s, lo, hi, rec=None, params: Optional[IbbParams] = N
                      etag[:e].copy(), {f: int(getattr(st_, f)) for f in STATS_FIELDS})
 
 
-def ibb_solve_batch(ctx: Context, systems, params=None, cap: int = 1 << 16):
-    """Solve many systems in one pass; returns a list of Result (one per system)."""
-    L = load_library()
+def _batch_inputs(systems, params):
     B = len(systems)
     refs = [_SysRef(s) for s in systems]
     arr = (IbbSystem * B)(*[r.c for r in refs])
@@ -360,6 +364,11 @@ def ibb_solve_batch(ctx: Context, systems, params=None, cap: int = 1 << 16):
     if params is None:
         params = [make_params(s.tol) for s in systems]
     parr = (IbbParams * B)(*params)
+    return refs, arr, lo, hi, parr
+
+
+def _batch_results(call, systems, cap, name):
+    B = len(systems)
     while True:
         olo = np.zeros((max(cap, 1), MAX_N))
         ohi = np.zeros((max(cap, 1), MAX_N))
@@ -367,19 +376,61 @@ def ibb_solve_batch(ctx: Context, systems, params=None, cap: int = 1 << 16):
         off = np.zeros(B + 1, dtype=np.int64)
         status = np.zeros(B, dtype=np.int32)
         stats = (IbbStats * B)()
-        st = L.ibb_solve_batch(ctx.handle, int(B), arr, _ptr(lo), _ptr(hi), parr, _ptr(olo), _ptr(ohi), _ptr(otag),
-                               int(cap), _ptr(off), _ptr(status), stats)
+        st = call(_ptr(olo), _ptr(ohi), _ptr(otag), int(cap), _ptr(off), _ptr(status), stats)
         if st == ERR_OUTPUT_CAPACITY:
             cap = int(off[-1])
             continue
         if st != OK:
-            raise RuntimeError(f"ibb_solve_batch: {ibb_strerror(st)}")
+            raise RuntimeError(f"{name}: {ibb_strerror(st)}")
         out = []
         for b, s in enumerate(systems):
             a, e = int(off[b]), int(off[b + 1])
             sd = {f: int(getattr(stats[b], f)) for f in STATS_FIELDS}
             out.append(Result(int(status[b]), olo[a:e, :s.n].copy(), ohi[a:e, :s.n].copy(), otag[a:e].copy(), sd))
         return out
+
+
+def ibb_solve_batch(ctx: Context, systems, params=None, cap: int = 1 << 16):
+    """Solve many systems in one pass; returns a list of Result (one per system)."""
+    L = load_library()
+    refs, arr, lo, hi, parr = _batch_inputs(systems, params)
+
+    def call(*outs):
+        return L.ibb_solve_batch(ctx.handle, int(len(systems)), arr, _ptr(lo), _ptr(hi), parr, *outs)
+
+    return _batch_results(call, systems, cap, "ibb_solve_batch")
+
+
+class BatchPlan:
+    """A batch recorded once (ibb_batch_plan_create) and replayed by run()."""
+
+    def __init__(self, ctx: Context, systems, params=None):
+        self._L = load_library()
+        self.systems = list(systems)
+        refs, arr, lo, hi, parr = _batch_inputs(self.systems, params)
+        h = C.c_void_p()
+        st = self._L.ibb_batch_plan_create(ctx.handle, int(len(self.systems)), arr, _ptr(lo), _ptr(hi), parr,
+                                           C.byref(h))
+        if st != OK:
+            raise RuntimeError(f"ibb_batch_plan_create: {ibb_strerror(st)}")
+        self.handle = h
+
+    def run(self, cap: int = 1 << 16):
+        def call(*outs):
+            return self._L.ibb_batch_plan_run(self.handle, *outs)
+
+        return _batch_results(call, self.systems, cap, "ibb_batch_plan_run")
+
+    def close(self):
+        if self.handle:
+            self._L.ibb_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

@@ -40,6 +40,7 @@ hipError_t launch_finalize(hipStream_t s, const Ctrl* c, long long out_cap, long
 const void* queue_kernel_ptr(int G);
 hipError_t launch_queue_init(hipStream_t s, unsigned long long* seq, long long cap, Ctrl* c, long long* level_sizes,
                              int level_cap);
+hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, long long count, unsigned long long v);
 hipError_t launch_selftest(hipStream_t s, int op, long long count, const double* x, const double* y,
                            double* out);
 }  // namespace ibb
@@ -556,21 +557,33 @@ BatchLayout batch_layout(int B, size_t blob_words, long long fcap, long long oca
 
 }  // namespace
 
-extern "C" int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const double* lo,
-                               const double* hi, const ibb_params* params, double* out_lo, double* out_hi,
-                               uint8_t* out_tag, int64_t cap, int64_t* out_off, int32_t* status,
-                               ibb_stats* stats) {
-  if (!ctx || B < 1 || !systems || !lo || !hi || !params || !out_off || !status || cap < 0 ||
-      (cap > 0 && (!out_lo || !out_hi || !out_tag)))
-    return IBB_ERR_INVALID_ARG;
-  if (hipSetDevice(ctx->device) != hipSuccess) return IBB_ERR_DEVICE;
-  std::vector<Compiled> comp((size_t)B);
-  std::vector<long long> boff((size_t)B, 0);
-  std::vector<int> nsys((size_t)B, 1);
-  std::vector<SysParams> sp((size_t)B);
-  std::vector<int> buckets[5];
+namespace {
+
+// Host side of a batch: every member validated and compiled, tables packed into
+// one blob, members grouped by lanes per box.
+struct BatchHost {
+  int B = 0;
   size_t words = 0;
+  std::vector<long long> boff;
+  std::vector<int> nsys;
+  std::vector<SysParams> sp;
+  std::vector<uint64_t> blob;
+  std::vector<double> lo16, hi16;
+  std::vector<int> bucket_list;
+  int bucket_start[5] = {0, 0, 0, 0, 0};
+  bool any = false;
+};
+
+int batch_prepare(int B, const ibb_system* systems, const double* lo, const double* hi, const ibb_params* params,
+                  int32_t* status, BatchHost& h) {
+  h.B = B;
+  std::vector<Compiled> comp((size_t)B);
+  h.boff.assign((size_t)B, 0);
+  h.nsys.assign((size_t)B, 1);
+  h.sp.assign((size_t)B, SysParams{});
+  std::vector<int> buckets[4];
   long long first_valid = -1;
+  h.words = 0;
   for (int b = 0; b < B; ++b) {
     status[b] = validate(&systems[b], lo + (size_t)b * kMaxN, hi + (size_t)b * kMaxN, &params[b]);
     if (status[b] != IBB_OK) continue;
@@ -579,185 +592,385 @@ extern "C" int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* system
     } catch (...) {
       return IBB_ERR_NO_MEMORY;
     }
-    boff[b] = (long long)words;
-    if (first_valid < 0) first_valid = (long long)words;
-    words += comp[b].blob.size();
-    nsys[b] = comp[b].n;
+    h.boff[b] = (long long)h.words;
+    if (first_valid < 0) first_valid = (long long)h.words;
+    h.words += comp[b].blob.size();
+    h.nsys[b] = comp[b].n;
     const ibb_params& p = params[b];
-    sp[b] = SysParams{p.tol, p.recontract_ratio, p.hs_max_width, p.max_boxes, p.split_mode, p.max_recontract};
+    h.sp[b] = SysParams{p.tol, p.recontract_ratio, p.hs_max_width, p.max_boxes, p.split_mode, p.max_recontract};
     const int G = comp[b].G;
     buckets[G == 2 ? 0 : G == 4 ? 1 : G == 8 ? 2 : 3].push_back(b);
   }
-  if (first_valid < 0) {
+  h.any = first_valid >= 0;
+  if (!h.any) return IBB_OK;
+  for (int b = 0; b < B; ++b)
+    if (status[b] != IBB_OK) h.boff[b] = first_valid;  // never stepped; any valid table
+  try {
+    h.blob.assign(h.words, 0);
+    h.lo16.assign((size_t)B * kMaxN, 0.0);
+    h.hi16.assign((size_t)B * kMaxN, 0.0);
+  } catch (...) {
+    return IBB_ERR_NO_MEMORY;
+  }
+  for (int b = 0; b < B; ++b)
+    if (status[b] == IBB_OK) std::memcpy(h.blob.data() + h.boff[b], comp[b].blob.data(), 8 * comp[b].blob.size());
+  for (int b = 0; b < B; ++b)
+    for (int k = 0; k < h.nsys[b]; ++k) {
+      h.lo16[(size_t)b * kMaxN + k] = lo[(size_t)b * kMaxN + k];
+      h.hi16[(size_t)b * kMaxN + k] = hi[(size_t)b * kMaxN + k];
+    }
+  h.bucket_list.clear();
+  for (int q = 0; q < 4; ++q) {
+    h.bucket_start[q] = (int)h.bucket_list.size();
+    h.bucket_list.insert(h.bucket_list.end(), buckets[q].begin(), buckets[q].end());
+  }
+  h.bucket_start[4] = (int)h.bucket_list.size();
+  return IBB_OK;
+}
+
+// Inputs of a batch into its workspace, and the derivative coefficients.
+int batch_upload(const BatchHost& h, char* w, const BatchLayout& L, hipStream_t s) {
+  const int B = h.B;
+  if (hipMemcpyAsync(w + L.blobs, h.blob.data(), 8 * h.words, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(w + L.boff, h.boff.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(w + L.sp, h.sp.data(), sizeof(SysParams) * B, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(w + L.nsys, h.nsys.data(), sizeof(int) * B, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(w + L.lo, h.lo16.data(), sizeof(double) * kMaxN * B, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(w + L.hi, h.hi16.data(), sizeof(double) * kMaxN * B, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(w + L.bucket, h.bucket_list.data(), sizeof(int) * h.bucket_list.size(), hipMemcpyHostToDevice,
+                     s) != hipSuccess)
+    return IBB_ERR_DEVICE;
+  if (launch_prep(s, reinterpret_cast<uint64_t*>(w + L.blobs), reinterpret_cast<const long long*>(w + L.boff), B) !=
+      hipSuccess)
+    return IBB_ERR_DEVICE;
+  return IBB_OK;
+}
+
+// The device work of one batch solve: counters cleared by fill kernels, then per
+// lane-count bucket the initial boxes and one persistent launch.  Contains no
+// memset and no host synchronisation, so it can be recorded into a graph.
+int batch_enqueue(ibb_ctx* ctx, const BatchHost& h, char* w, const BatchLayout& L, long long fcap, long long ocap,
+                  hipStream_t s) {
+  const int B = h.B;
+  auto D = [&](size_t off) { return w + off; };
+  if (launch_fill_u64(s, reinterpret_cast<unsigned long long*>(D(L.count_sys)), (long long)((L.ctrl - L.count_sys) / 8),
+                      0ull) != hipSuccess ||
+      launch_fill_u64(s, reinterpret_cast<unsigned long long*>(D(L.out_count)), 1, 0ull) != hipSuccess)
+    return IBB_ERR_DEVICE;
+  for (int q = 0; q < 4; ++q) {
+    const int m = h.bucket_start[q + 1] - h.bucket_start[q];
+    if (m == 0) continue;
+    const int G = 2 << q;
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(D(L.ctrl)) + q;
+    if (launch_batch_init(s, ctrl, reinterpret_cast<double*>(D(L.front0)), reinterpret_cast<uint32_t*>(D(L.meta0)),
+                          reinterpret_cast<uint32_t*>(D(L.sys0)), reinterpret_cast<const double*>(D(L.lo)),
+                          reinterpret_cast<const double*>(D(L.hi)),
+                          reinterpret_cast<const int*>(D(L.bucket)) + h.bucket_start[q], m, G,
+                          reinterpret_cast<const int*>(D(L.nsys)),
+                          reinterpret_cast<unsigned long long*>(D(L.count_sys)), B) != hipSuccess)
+      return IBB_ERR_DEVICE;
+    SolveArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.front[0] = reinterpret_cast<double*>(D(L.front0));
+    a.front[1] = reinterpret_cast<double*>(D(L.front1));
+    a.meta[0] = reinterpret_cast<uint32_t*>(D(L.meta0));
+    a.meta[1] = reinterpret_cast<uint32_t*>(D(L.meta1));
+    a.sys[0] = reinterpret_cast<uint32_t*>(D(L.sys0));
+    a.sys[1] = reinterpret_cast<uint32_t*>(D(L.sys1));
+    a.front_cap = fcap;
+    a.out_box = reinterpret_cast<double*>(D(L.out_box));
+    a.out_tag = reinterpret_cast<uint32_t*>(D(L.out_tag));
+    a.out_sys = reinterpret_cast<uint32_t*>(D(L.out_sys));
+    a.out_cap = ocap;
+    a.out_count = reinterpret_cast<unsigned long long*>(D(L.out_count));
+    a.out_stride = kMaxN;
+    a.ctrl = ctrl;
+    a.level_sizes = reinterpret_cast<long long*>(D(L.level));
+    a.level_cap = kLevelCap;
+    a.max_boxes = 1LL << 62;
+    a.timeout_ticks = ctx->clock_khz * 1000LL * 20;
+    a.blobs = reinterpret_cast<const uint64_t*>(D(L.blobs));
+    a.blob_off = reinterpret_cast<const long long*>(D(L.boff));
+    a.sp = reinterpret_cast<const SysParams*>(D(L.sp));
+    a.count_sys = reinterpret_cast<unsigned long long*>(D(L.count_sys));
+    a.cum_sys = reinterpret_cast<unsigned long long*>(D(L.cum_sys));
+    a.status_sys = reinterpret_cast<int*>(D(L.status_sys));
+    a.stats_sys = reinterpret_cast<unsigned long long*>(D(L.stats_sys));
+    a.B = B;
+    const void* fn = solve_kernel_ptr(G, true);
+    Geometry geo;
+    const int st = persistent_geometry(ctx, fn, 0, G, G, &geo);
+    if (st) return st;
+    a.nblocks = geo.blocks;
+    a.jrs = geo.jrs;
+    void* args[] = {&a};
+    if (hipLaunchCooperativeKernel(fn, dim3(geo.blocks), dim3(64 * geo.waves), args, (unsigned)geo.lds, s) !=
+        hipSuccess)
+      return IBB_ERR_DEVICE;
+  }
+  return IBB_OK;
+}
+
+// Results of a batch solve: statuses, counters, per-system sorted segments.
+// *grow_f / *grow_o report a frontier or output overflow (the caller re-runs).
+int batch_finish(const BatchHost& h, char* w, const BatchLayout& L, long long ocap, hipStream_t s, double* out_lo,
+                 double* out_hi, uint8_t* out_tag, int64_t cap, int64_t* out_off, int32_t* status, ibb_stats* stats,
+                 bool* grow_f, long long* grow_o) {
+  const int B = h.B;
+  auto D = [&](size_t off) { return w + off; };
+  *grow_f = false;
+  *grow_o = 0;
+  Ctrl ctrls[4];
+  unsigned long long M = 0;
+  if (hipMemcpyAsync(ctrls, D(L.ctrl), sizeof ctrls, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&M, D(L.out_count), sizeof M, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return IBB_ERR_DEVICE;
+  for (int q = 0; q < 4; ++q) {
+    if (h.bucket_start[q + 1] == h.bucket_start[q]) continue;
+    if (ctrls[q].status == IBB_ERR_QUEUE_OVERFLOW) *grow_f = true;
+    else if (ctrls[q].status != 0) return ctrls[q].status;
+  }
+  if (*grow_f) return IBB_OK;
+  if ((long long)M > ocap) {
+    *grow_o = (long long)M;
+    return IBB_OK;
+  }
+  std::vector<int> sst((size_t)B);
+  std::vector<unsigned long long> sstats((size_t)B * 8);
+  if (hipMemcpy(sst.data(), D(L.status_sys), sizeof(int) * B, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(sstats.data(), D(L.stats_sys), sizeof(unsigned long long) * 8 * B, hipMemcpyDeviceToHost) !=
+          hipSuccess)
+    return IBB_ERR_DEVICE;
+  // per-system output segments (boxes of failed systems are not returned)
+  std::vector<long long> seg((size_t)B + 1, 0);
+  for (int b = 0; b < B; ++b) {
+    if (status[b] == IBB_OK && sst[b] != 0) status[b] = sst[b];
+    const long long mb = (long long)(sstats[(size_t)b * 8 + 6] + sstats[(size_t)b * 8 + 7]);
+    seg[b + 1] = seg[b] + mb;
+    if (stats) {
+      ibb_stats& o = stats[b];
+      std::memset(&o, 0, sizeof o);
+      int64_t* f = &o.processed;
+      for (int k = 0; k < 8; ++k) f[k] = (int64_t)sstats[(size_t)b * 8 + k];
+    }
+  }
+  if (seg[B] != (long long)M) return IBB_ERR_DEVICE;  // counters disagree with the output list
+  out_off[0] = 0;
+  for (int b = 0; b < B; ++b) out_off[b + 1] = out_off[b] + (status[b] == IBB_OK ? seg[b + 1] - seg[b] : 0);
+  if (hipMemcpyAsync(D(L.seg_off), seg.data(), sizeof(long long) * (B + 1), hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      launch_fill_u64(s, reinterpret_cast<unsigned long long*>(D(L.cursor)), B, 0ull) != hipSuccess ||
+      launch_seg_sort(s, reinterpret_cast<const double*>(D(L.out_box)), reinterpret_cast<const uint32_t*>(D(L.out_tag)),
+                      reinterpret_cast<const uint32_t*>(D(L.out_sys)), (long long)M,
+                      reinterpret_cast<const long long*>(D(L.seg_off)),
+                      reinterpret_cast<unsigned long long*>(D(L.cursor)), reinterpret_cast<uint32_t*>(D(L.order)),
+                      reinterpret_cast<const int*>(D(L.nsys)), reinterpret_cast<double*>(D(L.s_lo)),
+                      reinterpret_cast<double*>(D(L.s_hi)), reinterpret_cast<uint8_t*>(D(L.s_tag))) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return IBB_ERR_DEVICE;
+  if (out_off[B] > cap) return IBB_ERR_OUTPUT_CAPACITY;
+  // one transfer of the sorted segments, then each successful system's
+  // segment to its place in the caller's arrays
+  std::vector<double> hlo((size_t)M * kMaxN), hhi((size_t)M * kMaxN);
+  std::vector<uint8_t> htag((size_t)M);
+  if (M > 0 &&
+      (hipMemcpy(hlo.data(), D(L.s_lo), sizeof(double) * kMaxN * M, hipMemcpyDeviceToHost) != hipSuccess ||
+       hipMemcpy(hhi.data(), D(L.s_hi), sizeof(double) * kMaxN * M, hipMemcpyDeviceToHost) != hipSuccess ||
+       hipMemcpy(htag.data(), D(L.s_tag), (size_t)M, hipMemcpyDeviceToHost) != hipSuccess))
+    return IBB_ERR_DEVICE;
+  for (int b = 0; b < B; ++b) {
+    if (status[b] != IBB_OK) continue;
+    const long long m = seg[b + 1] - seg[b];
+    if (m == 0) continue;
+    const size_t src = (size_t)seg[b], dst = (size_t)out_off[b];
+    std::memcpy(out_lo + dst * kMaxN, hlo.data() + src * kMaxN, sizeof(double) * kMaxN * m);
+    std::memcpy(out_hi + dst * kMaxN, hhi.data() + src * kMaxN, sizeof(double) * kMaxN * m);
+    std::memcpy(out_tag + dst, htag.data() + src, (size_t)m);
+  }
+  return IBB_OK;
+}
+
+bool batch_args_ok(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const double* lo, const double* hi,
+                   const ibb_params* params) {
+  return ctx && B >= 1 && systems && lo && hi && params;
+}
+
+bool batch_outputs_ok(int64_t cap, const double* out_lo, const double* out_hi, const uint8_t* out_tag,
+                      const int64_t* out_off, const int32_t* status) {
+  return out_off && status && cap >= 0 && (cap == 0 || (out_lo && out_hi && out_tag));
+}
+
+}  // namespace
+
+extern "C" int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const double* lo,
+                               const double* hi, const ibb_params* params, double* out_lo, double* out_hi,
+                               uint8_t* out_tag, int64_t cap, int64_t* out_off, int32_t* status,
+                               ibb_stats* stats) {
+  if (!batch_args_ok(ctx, B, systems, lo, hi, params) || !batch_outputs_ok(cap, out_lo, out_hi, out_tag, out_off, status))
+    return IBB_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return IBB_ERR_DEVICE;
+  BatchHost h;
+  int st = batch_prepare(B, systems, lo, hi, params, status, h);
+  if (st) return st;
+  if (!h.any) {
     for (int b = 0; b <= B; ++b) out_off[b] = 0;
     return IBB_OK;
   }
-  for (int b = 0; b < B; ++b)
-    if (status[b] != IBB_OK) boff[b] = first_valid;  // never stepped; any valid table
-  std::vector<uint64_t> blob(words);
-  for (int b = 0; b < B; ++b)
-    if (status[b] == IBB_OK) std::memcpy(blob.data() + boff[b], comp[b].blob.data(), 8 * comp[b].blob.size());
-  std::vector<double> lo16((size_t)B * kMaxN, 0.0), hi16((size_t)B * kMaxN, 0.0);
-  for (int b = 0; b < B; ++b)
-    for (int k = 0; k < nsys[b]; ++k) {
-      lo16[(size_t)b * kMaxN + k] = lo[(size_t)b * kMaxN + k];
-      hi16[(size_t)b * kMaxN + k] = hi[(size_t)b * kMaxN + k];
-    }
-  std::vector<int> bucket_list;
-  int bucket_start[5] = {0};
-  for (int q = 0; q < 4; ++q) {
-    bucket_start[q] = (int)bucket_list.size();
-    bucket_list.insert(bucket_list.end(), buckets[q].begin(), buckets[q].end());
-  }
-  bucket_start[4] = (int)bucket_list.size();
-
-  long long fcap = 1LL << 20, ocap = 1LL << 14;
+  // capacities sized for the batch up front: an overflow re-runs the whole batch
+  long long fcap = 1LL << 22, ocap = std::max<long long>(1LL << 15, 16LL * B);
   hipStream_t s = ctx->stream;
   for (int attempt = 0; attempt < 10; ++attempt) {
-    const BatchLayout L = batch_layout(B, words, fcap, ocap);
-    int st = ensure_device(&ctx->bws, &ctx->bws_bytes, L.total);
+    const BatchLayout L = batch_layout(B, h.words, fcap, ocap);
+    st = ensure_device(&ctx->bws, &ctx->bws_bytes, L.total);
     if (st) return st;
     char* w = static_cast<char*>(ctx->bws);
-    auto D = [&](size_t off) { return w + off; };
-    if (hipMemcpyAsync(D(L.blobs), blob.data(), 8 * words, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(D(L.boff), boff.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(D(L.sp), sp.data(), sizeof(SysParams) * B, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(D(L.nsys), nsys.data(), sizeof(int) * B, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(D(L.lo), lo16.data(), sizeof(double) * kMaxN * B, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(D(L.hi), hi16.data(), sizeof(double) * kMaxN * B, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(D(L.bucket), bucket_list.data(), sizeof(int) * bucket_list.size(), hipMemcpyHostToDevice,
-                       s) != hipSuccess ||
-        hipMemsetAsync(D(L.count_sys), 0, L.ctrl - L.count_sys, s) != hipSuccess ||
-        hipMemsetAsync(D(L.out_count), 0, L.order - L.out_count, s) != hipSuccess)
-      return IBB_ERR_DEVICE;
-    if (launch_prep(s, reinterpret_cast<uint64_t*>(D(L.blobs)), reinterpret_cast<const long long*>(D(L.boff)),
-                    B) != hipSuccess)
-      return IBB_ERR_DEVICE;
+    st = batch_upload(h, w, L, s);
+    if (st) return st;
     ctx->tune_pending = false;
     hipEventRecord(ctx->ev0, s);
-    for (int q = 0; q < 4; ++q) {
-      const int m = bucket_start[q + 1] - bucket_start[q];
-      if (m == 0) continue;
-      const int G = 2 << q;
-      Ctrl* ctrl = reinterpret_cast<Ctrl*>(D(L.ctrl)) + q;
-      if (launch_batch_init(s, ctrl, reinterpret_cast<double*>(D(L.front0)), reinterpret_cast<uint32_t*>(D(L.meta0)),
-                            reinterpret_cast<uint32_t*>(D(L.sys0)), reinterpret_cast<const double*>(D(L.lo)),
-                            reinterpret_cast<const double*>(D(L.hi)),
-                            reinterpret_cast<const int*>(D(L.bucket)) + bucket_start[q], m, G,
-                            reinterpret_cast<const int*>(D(L.nsys)),
-                            reinterpret_cast<unsigned long long*>(D(L.count_sys)), B) != hipSuccess)
-        return IBB_ERR_DEVICE;
-      SolveArgs a;
-      std::memset(&a, 0, sizeof a);
-      a.front[0] = reinterpret_cast<double*>(D(L.front0));
-      a.front[1] = reinterpret_cast<double*>(D(L.front1));
-      a.meta[0] = reinterpret_cast<uint32_t*>(D(L.meta0));
-      a.meta[1] = reinterpret_cast<uint32_t*>(D(L.meta1));
-      a.sys[0] = reinterpret_cast<uint32_t*>(D(L.sys0));
-      a.sys[1] = reinterpret_cast<uint32_t*>(D(L.sys1));
-      a.front_cap = fcap;
-      a.out_box = reinterpret_cast<double*>(D(L.out_box));
-      a.out_tag = reinterpret_cast<uint32_t*>(D(L.out_tag));
-      a.out_sys = reinterpret_cast<uint32_t*>(D(L.out_sys));
-      a.out_cap = ocap;
-      a.out_count = reinterpret_cast<unsigned long long*>(D(L.out_count));
-      a.out_stride = kMaxN;
-      a.ctrl = ctrl;
-      a.level_sizes = reinterpret_cast<long long*>(D(L.level));
-      a.level_cap = kLevelCap;
-      a.max_boxes = 1LL << 62;
-      a.timeout_ticks = ctx->clock_khz * 1000LL * 20;
-      a.blobs = reinterpret_cast<const uint64_t*>(D(L.blobs));
-      a.blob_off = reinterpret_cast<const long long*>(D(L.boff));
-      a.sp = reinterpret_cast<const SysParams*>(D(L.sp));
-      a.count_sys = reinterpret_cast<unsigned long long*>(D(L.count_sys));
-      a.cum_sys = reinterpret_cast<unsigned long long*>(D(L.cum_sys));
-      a.status_sys = reinterpret_cast<int*>(D(L.status_sys));
-      a.stats_sys = reinterpret_cast<unsigned long long*>(D(L.stats_sys));
-      a.B = B;
-      const void* fn = solve_kernel_ptr(G, true);
-      Geometry geo;
-      st = persistent_geometry(ctx, fn, 0, G, G, &geo);
-      if (st) return st;
-      a.nblocks = geo.blocks;
-      a.jrs = geo.jrs;
-      void* args[] = {&a};
-      if (hipLaunchCooperativeKernel(fn, dim3(geo.blocks), dim3(64 * geo.waves), args, (unsigned)geo.lds, s) !=
-          hipSuccess)
-        return IBB_ERR_DEVICE;
-    }
+    st = batch_enqueue(ctx, h, w, L, fcap, ocap, s);
+    if (st) return st;
     hipEventRecord(ctx->ev1, s);
     ctx->timed_pending = true;
-    Ctrl ctrls[4];
-    unsigned long long M = 0;
-    if (hipMemcpyAsync(ctrls, D(L.ctrl), sizeof ctrls, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(&M, D(L.out_count), sizeof M, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return IBB_ERR_DEVICE;
-    bool overflow = false;
-    for (int q = 0; q < 4; ++q) {
-      if (bucket_start[q + 1] == bucket_start[q]) continue;
-      if (ctrls[q].status == IBB_ERR_QUEUE_OVERFLOW) overflow = true;
-      else if (ctrls[q].status != 0) return ctrls[q].status;
-    }
-    if (overflow) {
+    bool grow_f = false;
+    long long grow_o = 0;
+    st = batch_finish(h, w, L, ocap, s, out_lo, out_hi, out_tag, cap, out_off, status, stats, &grow_f, &grow_o);
+    if (st) return st;
+    if (grow_f) {
       fcap *= 4;
       continue;
     }
-    if ((long long)M > ocap) {
-      ocap = (long long)M;
+    if (grow_o) {
+      ocap = grow_o;
       continue;
-    }
-    std::vector<int> sst((size_t)B);
-    std::vector<unsigned long long> sstats((size_t)B * 8);
-    if (hipMemcpy(sst.data(), D(L.status_sys), sizeof(int) * B, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(sstats.data(), D(L.stats_sys), sizeof(unsigned long long) * 8 * B, hipMemcpyDeviceToHost) !=
-            hipSuccess)
-      return IBB_ERR_DEVICE;
-    // per-system output segments (boxes of failed systems are not returned)
-    std::vector<long long> seg((size_t)B + 1, 0);
-    for (int b = 0; b < B; ++b) {
-      if (status[b] == IBB_OK && sst[b] != 0) status[b] = sst[b];
-      const long long mb = (long long)(sstats[(size_t)b * 8 + 6] + sstats[(size_t)b * 8 + 7]);
-      seg[b + 1] = seg[b] + mb;
-      if (stats) {
-        ibb_stats& o = stats[b];
-        std::memset(&o, 0, sizeof o);
-        int64_t* f = &o.processed;
-        for (int k = 0; k < 8; ++k) f[k] = (int64_t)sstats[(size_t)b * 8 + k];
-      }
-    }
-    if (seg[B] != (long long)M) return IBB_ERR_DEVICE;  // counters disagree with the output list
-    // result offsets: failed systems contribute no boxes
-    out_off[0] = 0;
-    for (int b = 0; b < B; ++b) out_off[b + 1] = out_off[b] + (status[b] == IBB_OK ? seg[b + 1] - seg[b] : 0);
-    if (hipMemcpyAsync(D(L.seg_off), seg.data(), sizeof(long long) * (B + 1), hipMemcpyHostToDevice, s) !=
-            hipSuccess ||
-        launch_seg_sort(s, reinterpret_cast<const double*>(D(L.out_box)), reinterpret_cast<const uint32_t*>(D(L.out_tag)),
-                        reinterpret_cast<const uint32_t*>(D(L.out_sys)), (long long)M,
-                        reinterpret_cast<const long long*>(D(L.seg_off)),
-                        reinterpret_cast<unsigned long long*>(D(L.cursor)), reinterpret_cast<uint32_t*>(D(L.order)),
-                        reinterpret_cast<const int*>(D(L.nsys)), reinterpret_cast<double*>(D(L.s_lo)),
-                        reinterpret_cast<double*>(D(L.s_hi)), reinterpret_cast<uint8_t*>(D(L.s_tag))) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return IBB_ERR_DEVICE;
-    if (out_off[B] > cap) return IBB_ERR_OUTPUT_CAPACITY;
-    // copy each successful system's segment
-    for (int b = 0; b < B; ++b) {
-      if (status[b] != IBB_OK) continue;
-      const long long m = seg[b + 1] - seg[b];
-      if (m == 0) continue;
-      const size_t src = (size_t)seg[b], dst = (size_t)out_off[b];
-      if (hipMemcpy(out_lo + dst * kMaxN, D(L.s_lo) + src * kMaxN * sizeof(double), sizeof(double) * kMaxN * m,
-                    hipMemcpyDeviceToHost) != hipSuccess ||
-          hipMemcpy(out_hi + dst * kMaxN, D(L.s_hi) + src * kMaxN * sizeof(double), sizeof(double) * kMaxN * m,
-                    hipMemcpyDeviceToHost) != hipSuccess ||
-          hipMemcpy(out_tag + dst, D(L.s_tag) + src, (size_t)m, hipMemcpyDeviceToHost) != hipSuccess)
-        return IBB_ERR_DEVICE;
     }
     return IBB_OK;
   }
   return IBB_ERR_NO_MEMORY;
+}
+
+// A batch prepared once and solved many times: inputs uploaded and the device
+// work recorded into a graph at creation; each run replays the graph.
+struct ibb_batch_plan {
+  ibb_ctx* ctx = nullptr;
+  BatchHost h;
+  std::vector<int32_t> status0;  // validation status of each member
+  long long fcap = 0, ocap = 0;
+  BatchLayout L{};
+  void* ws = nullptr;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void plan_release_graph(ibb_batch_plan* p) {
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+}
+
+// (Re)allocate the plan's workspace for its capacities, upload, record.
+int plan_build(ibb_batch_plan* p) {
+  plan_release_graph(p);
+  if (p->ws) hipFree(p->ws);
+  p->ws = nullptr;
+  p->L = batch_layout(p->h.B, p->h.words, p->fcap, p->ocap);
+  if (hipMalloc(&p->ws, p->L.total) != hipSuccess) {
+    p->ws = nullptr;
+    return IBB_ERR_NO_MEMORY;
+  }
+  char* w = static_cast<char*>(p->ws);
+  int st = batch_upload(p->h, w, p->L, p->stream);
+  if (st) return st;
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return IBB_ERR_DEVICE;
+  if (hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return IBB_ERR_DEVICE;
+  st = batch_enqueue(p->ctx, p->h, w, p->L, p->fcap, p->ocap, p->stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(p->stream, &g);
+  if (st) {
+    if (g) hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess || !g) return IBB_ERR_UNSUPPORTED;
+  p->graph = g;
+  if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    p->exec = nullptr;
+    return IBB_ERR_UNSUPPORTED;
+  }
+  return IBB_OK;
+}
+
+}  // namespace
+
+extern "C" int ibb_batch_plan_create(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const double* lo,
+                                     const double* hi, const ibb_params* params, ibb_batch_plan** out) {
+  if (!out) return IBB_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!batch_args_ok(ctx, B, systems, lo, hi, params)) return IBB_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return IBB_ERR_DEVICE;
+  ibb_batch_plan* p = new (std::nothrow) ibb_batch_plan();
+  if (!p) return IBB_ERR_NO_MEMORY;
+  p->ctx = ctx;
+  p->status0.assign((size_t)B, 0);
+  int st = batch_prepare(B, systems, lo, hi, params, p->status0.data(), p->h);
+  if (!st && hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess) {
+    p->stream = nullptr;
+    st = IBB_ERR_DEVICE;
+  }
+  p->fcap = 1LL << 22;
+  p->ocap = std::max<long long>(1LL << 15, 16LL * B);
+  if (!st && p->h.any) st = plan_build(p);
+  if (st) {
+    ibb_batch_plan_destroy(p);
+    return st;
+  }
+  *out = p;
+  return IBB_OK;
+}
+
+extern "C" int ibb_batch_plan_run(ibb_batch_plan* p, double* out_lo, double* out_hi, uint8_t* out_tag, int64_t cap,
+                                  int64_t* out_off, int32_t* status, ibb_stats* stats) {
+  if (!p || !batch_outputs_ok(cap, out_lo, out_hi, out_tag, out_off, status)) return IBB_ERR_INVALID_ARG;
+  const int B = p->h.B;
+  for (int b = 0; b < B; ++b) status[b] = p->status0[b];
+  if (!p->h.any) {
+    for (int b = 0; b <= B; ++b) out_off[b] = 0;
+    return IBB_OK;
+  }
+  if (hipSetDevice(p->ctx->device) != hipSuccess) return IBB_ERR_DEVICE;
+  ibb_ctx* ctx = p->ctx;
+  for (int attempt = 0; attempt < 10; ++attempt) {
+    ctx->tune_pending = false;
+    hipEventRecord(ctx->ev0, p->stream);
+    if (hipGraphLaunch(p->exec, p->stream) != hipSuccess) return IBB_ERR_DEVICE;
+    hipEventRecord(ctx->ev1, p->stream);
+    ctx->timed_pending = true;
+    bool grow_f = false;
+    long long grow_o = 0;
+    for (int b = 0; b < B; ++b) status[b] = p->status0[b];
+    int st = batch_finish(p->h, static_cast<char*>(p->ws), p->L, p->ocap, p->stream, out_lo, out_hi, out_tag, cap,
+                          out_off, status, stats, &grow_f, &grow_o);
+    if (st) return st;
+    if (!grow_f && !grow_o) return IBB_OK;
+    if (grow_f) p->fcap *= 4;
+    if (grow_o) p->ocap = grow_o;
+    st = plan_build(p);
+    if (st) return st;
+  }
+  return IBB_ERR_NO_MEMORY;
+}
+
+extern "C" void ibb_batch_plan_destroy(ibb_batch_plan* p) {
+  if (!p) return;
+  if (p->stream) hipStreamSynchronize(p->stream);
+  plan_release_graph(p);
+  if (p->ws) hipFree(p->ws);
+  if (p->stream) hipStreamDestroy(p->stream);
+  delete p;
 }
 
 extern "C" {

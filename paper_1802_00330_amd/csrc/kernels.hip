@@ -1096,6 +1096,13 @@ queue_kernel(SolveArgs a) {
   }
 }
 
+// Fills count 64-bit words with v (a kernel rather than a memset, so that the
+// fill can be recorded into a graph and replayed).
+__global__ void fill_u64_kernel(unsigned long long* p, long long count, unsigned long long v) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
+}
+
 // Ring of a work-queue search: every slot free for its first item, except
 // slot 0, which holds the initial box (written by init_kernel); no box stepped.
 __global__ void queue_init_kernel(unsigned long long* seq, long long cap, Ctrl* c, long long* level_sizes,
@@ -1349,6 +1356,13 @@ hipError_t launch_sort(hipStream_t s, const double* box, const uint32_t* tag, co
 hipError_t launch_finalize(hipStream_t s, const Ctrl* c, long long out_cap, long long* info,
                            const long long* depth_counts, int level_cap) {
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, s, c, out_cap, info, depth_counts, level_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, long long count, unsigned long long v) {
+  if (count <= 0) return hipSuccess;
+  const int blocks = (int)std::min<long long>((count + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks), dim3(256), 0, s, p, count, v);
   return hipGetLastError();
 }
 

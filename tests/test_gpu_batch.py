@@ -57,3 +57,35 @@ def test_batch_invalid_member(gpu_ctx, oracle_lib):
     res = P.ibb_solve_batch(gpu_ctx, [bad, good])
     assert res[0].status == P.ERR_INVALID_ARG
     assert_same(res[1], oracle_lib.solve(good), "after invalid")
+
+
+def test_batch_plan_replays_equal_eager_and_oracle(gpu_ctx, oracle_lib):
+    """A recorded batch plan replayed three times, with other device work and
+    synchronisations in between: every replay equals the eager batch solve and
+    the oracle, member by member (an invalid member keeps its status)."""
+    import torch
+
+    import paper_1802_00330_amd as P
+    systems = _mixed_systems()
+    bad = W.circle_line()
+    bad.coef[0] = float("inf")
+    systems = systems[:5] + [bad] + systems[5:]
+    eager = P.ibb_solve_batch(gpu_ctx, systems)
+    ref = [oracle_lib.solve(s) if k != 5 else None for k, s in enumerate(systems)]
+    plan = P.BatchPlan(gpu_ctx, systems)
+    try:
+        for rep in range(3):
+            print(f"[batch-plan] replay {rep}", flush=True)
+            res = plan.run()
+            assert res[5].status == P.ERR_INVALID_ARG and len(res[5].tag) == 0
+            for k, (r, e) in enumerate(zip(res, eager)):
+                assert_same(r, e, f"replay {rep} member {k} vs eager")
+                if ref[k] is not None:
+                    assert_same(r, ref[k], f"replay {rep} member {k} vs oracle")
+            # the program's own work between replays
+            P.solve(gpu_ctx, systems[0])
+            x = torch.arange(1 << 16, dtype=torch.float64, device="cuda")
+            assert float(x.sum().item()) == float((1 << 16) * ((1 << 16) - 1) // 2)
+            torch.cuda.synchronize()
+    finally:
+        plan.close()
