@@ -75,13 +75,25 @@ def batched_leg(ctx, P, W, count, budget, plain_sample, log):
         pn += r.stats["processed"]
     pdt = time.perf_counter() - t
     bn = sum(r.stats["processed"] for r in res[:plain_sample])
+    # the same batch recorded once and replayed from its graph
+    plan = P.BatchPlan(ctx, systems, params)
+    plan.run()  # first replay
+    t = time.perf_counter()
+    rres = plan.run()
+    rdt = time.perf_counter() - t
+    rkms = P.ibb_last_kernel_ms(ctx)
+    plan.close()
+    same = all(a.status == b.status and a.stats == b.stats and np.array_equal(a.lo, b.lo)
+               and np.array_equal(a.hi, b.hi) and np.array_equal(a.tag, b.tag) for a, b in zip(rres, res))
     return {"systems": count, "budget_nodes_per_system": budget, "completed": done,
             "over_budget": count - done, "tree_nodes": nodes, "seconds": dt, "kernel_ms": kms,
             "boxes_per_s": nodes / dt, "solves_per_s": count / dt,
             "plain": {"systems": plain_sample, "tree_nodes": pn, "seconds": pdt, "boxes_per_s": pn / pdt,
                       "solves_per_s": plain_sample / pdt},
             "batched_vs_plain_boxes_per_s": (nodes / dt) / (pn / pdt) if pn else None,
-            "same_nodes_as_plain": bool(pn == bn)}
+            "same_nodes_as_plain": bool(pn == bn),
+            "graph_replay": {"seconds": rdt, "device_ms": rkms, "boxes_per_s": nodes / rdt,
+                             "solves_per_s": count / rdt, "identical_to_batch": bool(same)}}
 
 
 def served_leg(ctx, P, W, rate, duration, log):
