@@ -39,7 +39,7 @@ __device__ __forceinline__ iv imul(iv x, iv y) {
   double u2 = rmul(x.lo, y.nhi);       // R(-a d)
   double u3 = rmul(x.nhi, y.lo);       // R(-b c)
   double u4 = rmul_neg(x.nhi, y.nhi);  // R(-b d)
-  return {fmin(fmin(l1, l2), fmin(l3, l4)), fmin(fmin(u1, u2), fmin(u3, u4))};
+  return {dmin(dmin(l1, l2), dmin(l3, l4)), dmin(dmin(u1, u2), dmin(u3, u4))};
 }
 
 // Point times interval (the four products reduce to two by the sign of y).
@@ -50,23 +50,24 @@ __device__ __forceinline__ iv pmul(double y, iv x) {
   return {rmul_abs(y, a), rmul_abs(y, b)};
 }
 
-// t <- R(t u), p-1 times, starting from s (left-to-right chained bound).
-__device__ __forceinline__ double chain(double s, double u, int p) {
-  double t = s;
-  for (int i = 1; i < p; ++i) t = rmul(t, u);
-  return t;
-}
-
-// Power X^p, p >= 1.  Odd powers are monotone: each endpoint e maps to the
-// chain e * |e| * ... .  Even powers are taken over |X|: [mn^p, m^p] with
-// m = max |endpoint| and mn = min |endpoint| (0 when X straddles 0).
+// Power X^p, p >= 1, each bound a left-to-right chain t <- R(t u) of p-1
+// products.  Odd powers are monotone: each endpoint e maps to the chain
+// e * |e| * ... (p = 1 is the empty chain).  Even powers are taken over |X|:
+// [mn^p, m^p] with m = max |endpoint| and mn = min |endpoint| (0 when X
+// straddles 0).  The two cases differ only in the chains' starting values,
+// so lanes with different exponents do not branch.
 __device__ __forceinline__ iv ipow(iv x, int p) {
-  if (p == 1) return x;
-  if (p & 1) return {chain(x.lo, fabs(x.lo), p), chain(x.nhi, fabs(x.nhi), p)};
-  double al = fabs(x.lo), ah = fabs(x.nhi);
-  double m = fmax(al, ah);
-  double mn = (x.lo >= 0.0 || x.nhi >= 0.0) ? fmin(al, ah) : 0.0;
-  return {chain(mn, mn, p), chain(-m, m, p)};
+  const double al = fabs(x.lo), ah = fabs(x.nhi);
+  const bool odd = (p & 1) != 0;
+  const double m = dmax(al, ah);
+  const double mn = (x.lo >= 0.0 || x.nhi >= 0.0) ? dmin(al, ah) : 0.0;
+  double a = odd ? x.lo : mn, b = odd ? x.nhi : -m;
+  const double ua = odd ? al : mn, ub = odd ? ah : m;
+  for (int i = 1; i < p; ++i) {
+    a = rmul(a, ua);
+    b = rmul(b, ub);
+  }
+  return {a, b};
 }
 
 // Midpoint (eq 2.5): R(R(a + b) * 0.5), which lies in [a, b].

@@ -70,6 +70,20 @@ __device__ __forceinline__ double rfma_na(double a, double b, double c) {  // R(
   return r;
 }
 
+// Minimum / maximum of two non-NaN doubles: the instructions the compiler
+// would choose, written out so that it adds no canonicalising copies of
+// operands produced by the asm statements above.
+__device__ __forceinline__ double dmin(double a, double b) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double dmax(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 __device__ __forceinline__ double bits_to_f64(uint64_t u) { return __longlong_as_double((long long)u); }
 __device__ __forceinline__ uint64_t f64_to_bits(double d) { return (uint64_t)__double_as_longlong(d); }
 
