@@ -183,7 +183,7 @@ void compile(const ibb_system* s, Compiled& c) {
 
 // Device workspace partition of one solve.
 struct WsLayout {
-  size_t ctrl, level, blob, box, front0, front1, meta0, meta1, out_box, out_tag, seq, total;
+  size_t ctrl, level, blob, box, front0, front1, meta0, meta1, out_box, out_tag, seq, stage_box, stage_meta, total;
 };
 
 WsLayout ws_layout(int n, size_t blob_words, long long frontier_cap, long long out_cap) {
@@ -206,6 +206,8 @@ WsLayout ws_layout(int n, size_t blob_words, long long frontier_cap, long long o
   L.out_box = take(sizeof(double) * 2 * G * (size_t)out_cap);
   L.out_tag = take(sizeof(uint32_t) * (size_t)out_cap);
   L.seq = take(sizeof(unsigned long long) * (size_t)frontier_cap);
+  L.stage_box = take(sizeof(double) * 2 * 128 * (size_t)kStageWaves);  // 2W * G = 128 rows per wave
+  L.stage_meta = take(sizeof(uint32_t) * 64 * (size_t)kStageWaves);     // 2W <= 64 records per wave
   L.total = o;
   return L;
 }
@@ -374,6 +376,8 @@ int launch_search(ibb_ctx* ctx, const Compiled& c, const ibb_params* p, char* ws
     a.front_cap = ring_capacity(frontier_cap);
     a.qseq = reinterpret_cast<unsigned long long*>(ws + L.seq);
   }
+  a.stage_box = reinterpret_cast<double*>(ws + L.stage_box);
+  a.stage_meta = reinterpret_cast<uint32_t*>(ws + L.stage_meta);
 
   const void* fn = queue ? queue_kernel_ptr(G) : solve_kernel_ptr(G, false);
   const size_t tbytes = (table_lds_bytes(n, c.T, c.TD) + 15) & ~size_t(15);
@@ -381,6 +385,7 @@ int launch_search(ibb_ctx* ctx, const Compiled& c, const ibb_params* p, char* ws
   {
     const int gst = persistent_geometry(ctx, fn, tbytes, G, n, &geo);
     if (gst) return gst;
+    if ((long long)geo.blocks * geo.waves > kStageWaves) return IBB_ERR_UNSUPPORTED;
   }
   a.nblocks = geo.blocks;
   a.jrs = geo.jrs;

@@ -341,22 +341,74 @@ struct QueueLocal {
   long long pend = 0;
 };
 
+// Work-queue bookkeeping once a wave has read its groups' boxes: the slots are
+// freed for the items one ring length later, and the boxes are counted by depth.
+__device__ __forceinline__ void queue_after_load(const SolveArgs& a, long long idx, bool valid, uint32_t meta, int r,
+                                                 QueueLocal* ql) {
+  const int lane = __lane_id();
+  const unsigned long long qmask = (unsigned long long)a.front_cap - 1ull;
+  // the slot is read (the loads above are complete once this wave's release
+  // fence returns): free it for the item one ring length later
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  if (valid && r == 0)
+    __hip_atomic_store(&a.qseq[(unsigned long long)idx & qmask], (unsigned long long)idx + qmask + 1ull,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // boxes per depth (the round sizes of Alg. 1): runs of one depth are
+  // counted in registers and added when the depth changes
+  const unsigned depth = meta >> 16;
+  const bool lead = valid && r == 0;
+  const uint64_t vm = __ballot(lead);
+  if (vm) {
+    const unsigned d0 = __shfl(depth, __ffsll((long long)vm) - 1, 64);
+    const bool same = __ballot(lead && depth == d0) == vm;
+    const unsigned long long nv = (unsigned long long)__popcll(vm);
+    if (same && (d0 == ql->run_depth || ql->run_count == 0)) {
+      ql->run_depth = d0;
+      ql->run_count += nv;
+    } else if (same) {
+      if (lane == 0 && ql->run_depth < (unsigned)a.level_cap)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&a.level_sizes[ql->run_depth]), ql->run_count);
+      ql->run_depth = d0;
+      ql->run_count = nv;
+    } else if (lead && depth < (unsigned)a.level_cap) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(&a.level_sizes[depth]), 1ull);
+    }
+    if (d0 + 1 > ql->depth_max) ql->depth_max = d0 + 1;
+    if (!same) {
+      unsigned dm = lead ? depth + 1 : 0u;
+      for (int o = 32; o > 0; o >>= 1) dm = max(dm, (unsigned)__shfl_xor((int)dm, o, 64));
+      if (dm > ql->depth_max) ql->depth_max = dm;
+    }
+  }
+}
+
+// A wave's staging ring of boxes that passed the exclusion test: 2W records
+// (box rows (lo, -hi) and the box record) in device memory, indexed by
+// monotone counters held by the wave.
+struct Stage {
+  double* box;     // [2W][G][2]
+  uint32_t* meta;  // [2W]
+  unsigned long long head = 0, tail = 0;
+};
+
 // Level mode (QUEUE = false): boxes [base, base + W) of level `level` in
 // front[cur], children appended to front[cur ^ 1].  Work-queue mode: each
 // group's box is in ring slot qslot (valid when qvalid), children are
-// reserved at the ring's tail and published through qseq.
-template <int G, bool MULTI, bool QUEUE = false>
+// reserved at the ring's tail and published through qseq.  STAGED: the
+// boxes are the next (at most W) records of the wave's staging ring, which
+// passed the exclusion test and were counted when they were screened.
+template <int G, bool MULTI, bool QUEUE = false, bool STAGED = false>
 __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, Scratch<G>& S, const JView J,
                           long long base,
                           long long cnt, int cur, int level, unsigned long long* next_count,
                           StepCounters& sc, long long qslot = 0, bool qvalid = false,
-                          QueueLocal* ql = nullptr) {
+                          QueueLocal* ql = nullptr, Stage* stg = nullptr) {
   const int lane = __lane_id();
   const int g = lane / G;
   const int r = lane % G;
   const unsigned long long qmask = (unsigned long long)a.front_cap - 1ull;
   const long long idx = QUEUE ? qslot : base + g;
-  bool valid = QUEUE ? qvalid : idx < cnt;
+  bool valid = STAGED ? (stg->head + (unsigned long long)g < stg->tail) : (QUEUE ? qvalid : idx < cnt);
   // the group's system: its table, size and parameters
   LTable T = Tl;
   uint32_t sysid = 0;
@@ -386,11 +438,20 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
   }
   const int n = T.n;
   const bool row_ok = r < n;
-  double* const dbg = (a.dbg && idx == 0 && valid) ? a.dbg : nullptr;
+  double* const dbg = (a.dbg && (STAGED ? g == 0 : idx == 0) && valid) ? a.dbg : nullptr;
 
   // ---- load the box and its record
   uint32_t meta = 0;
-  if (valid) {
+  if (STAGED) {
+    if (valid) {
+      const size_t at = (size_t)((stg->head + (unsigned long long)g) % (unsigned long long)(2 * (64 / G)));
+      if (row_ok) {
+        const double* src = stg->box + (at * G + r) * 2;
+        S.X[g][r] = iv{src[0], src[1]};
+      }
+      meta = stg->meta[at];
+    }
+  } else if (valid) {
     const size_t at = QUEUE ? (size_t)((unsigned long long)idx & qmask) : (size_t)idx;
     const int buf = QUEUE ? 0 : cur;
     if (row_ok) {
@@ -402,45 +463,11 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
   const bool proven = meta & 1u;
   const int rc = (int)((meta >> 8) & 0xFF);
   wave_lds_sync();
-  if (QUEUE) {
-    // the slot is read (the loads above are complete once this wave's release
-    // fence returns): free it for the item one ring length later
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    if (valid && r == 0)
-      __hip_atomic_store(&a.qseq[(unsigned long long)idx & qmask], (unsigned long long)idx + qmask + 1ull,
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // boxes per depth (the round sizes of Alg. 1): runs of one depth are
-    // counted in registers and added when the depth changes
-    const unsigned depth = meta >> 16;
-    const bool lead = valid && r == 0;
-    const uint64_t vm = __ballot(lead);
-    if (vm) {
-      const unsigned d0 = __shfl(depth, __ffsll((long long)vm) - 1, 64);
-      const bool same = __ballot(lead && depth == d0) == vm;
-      const unsigned long long nv = (unsigned long long)__popcll(vm);
-      if (same && (d0 == ql->run_depth || ql->run_count == 0)) {
-        ql->run_depth = d0;
-        ql->run_count += nv;
-      } else if (same) {
-        if (lane == 0 && ql->run_depth < (unsigned)a.level_cap)
-          atomicAdd(reinterpret_cast<unsigned long long*>(&a.level_sizes[ql->run_depth]), ql->run_count);
-        ql->run_depth = d0;
-        ql->run_count = nv;
-      } else if (lead && depth < (unsigned)a.level_cap) {
-        atomicAdd(reinterpret_cast<unsigned long long*>(&a.level_sizes[depth]), 1ull);
-      }
-      if (d0 + 1 > ql->depth_max) ql->depth_max = d0 + 1;
-      if (!same) {
-        unsigned dm = lead ? depth + 1 : 0u;
-        for (int o = 32; o > 0; o >>= 1) dm = max(dm, (unsigned)__shfl_xor((int)dm, o, 64));
-        if (dm > ql->depth_max) ql->depth_max = dm;
-      }
-    }
-  }
+  if (QUEUE && !STAGED) queue_after_load(a, idx, valid, meta, r, ql);
 
   // ---- exclusion test (Def. 2): some F_i(X) excludes 0
   bool excl_row = false;
-  if (valid && !proven && row_ok) {
+  if (!STAGED && valid && !proven && row_ok) {
     const iv f = eval_equation(T, r, S.X[g]);
     excl_row = f.lo > 0.0 || f.nhi > 0.0;
   }
@@ -781,8 +808,10 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
       sys_add(a.pending_sys, sysid, 0xFFFFFFFFu, dropped);
     }
   }
-  sc.s[kProcessed] += __popcll(__ballot(leader));
-  sc.s[kExclEval] += __popcll(__ballot(leader && excluded));
+  if (!STAGED) {
+    sc.s[kProcessed] += __popcll(__ballot(leader));
+    sc.s[kExclEval] += __popcll(__ballot(leader && excluded));
+  }
   sc.s[kExclHs] += __popcll(__ballot(leader && hs_empty));
   sc.s[kHsSkipped] += __popcll(__ballot(leader && active && !run));
   sc.s[kRecontract] += __popcll(__ballot(leader && kind == 1));
@@ -899,6 +928,68 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
   wave_lds_sync();
 }
 
+// Stage one of a step for one system: the boxes of a tile (level mode: boxes
+// [base, base + W) of front[cur]; work-queue mode: the groups' ring items) are
+// read and tested for exclusion (Def. 2); every box is counted as processed,
+// excluded ones as excluded by evaluation, and the others (proven boxes skip
+// the test) are appended to the wave's staging ring, to be stepped W at a time
+// by step_tile<..., STAGED> so that no group of a wave idles through the
+// contraction because its box was excluded.
+template <int G, bool QUEUE>
+__device__ __forceinline__ void screen_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, long long base,
+                                            long long cnt, int cur, StepCounters& sc, long long qslot, bool qvalid,
+                                            QueueLocal* ql, Stage& stg) {
+  constexpr int W = 64 / G;
+  const int lane = __lane_id();
+  const int g = lane / G;
+  const int r = lane % G;
+  const unsigned long long qmask = (unsigned long long)a.front_cap - 1ull;
+  const long long idx = QUEUE ? qslot : base + g;
+  const bool valid = QUEUE ? qvalid : idx < cnt;
+  const int n = T.n;
+  const bool row_ok = r < n;
+  uint32_t meta = 0;
+  if (valid) {
+    const size_t at = QUEUE ? (size_t)((unsigned long long)idx & qmask) : (size_t)idx;
+    const int buf = QUEUE ? 0 : cur;
+    if (row_ok) {
+      const double* src = a.front[buf] + (at * G + r) * 2;
+      S.X[g][r] = iv{src[0], src[1]};
+    }
+    meta = a.meta[buf][at];
+  }
+  const bool proven = meta & 1u;
+  wave_lds_sync();
+  if (QUEUE) queue_after_load(a, idx, valid, meta, r, ql);
+  bool excl_row = false;
+  if (valid && !proven && row_ok) {
+    const iv f = eval_equation(T, r, S.X[g]);
+    excl_row = f.lo > 0.0 || f.nhi > 0.0;
+  }
+  const bool excluded = group_bits<G>(__ballot(excl_row), g) != 0;
+  const bool leader = valid && r == 0;
+  sc.s[kProcessed] += __popcll(__ballot(leader));
+  const unsigned n_excl = (unsigned)__popcll(__ballot(leader && excluded));
+  sc.s[kExclEval] += n_excl;
+  if (QUEUE) ql->pend -= (long long)n_excl;  // stepped boxes without children
+  // survivors into the staging ring, in group order
+  const bool keep = valid && !excluded;
+  const uint64_t km = __ballot(keep && r == 0);
+  if (keep) {
+    const uint64_t below = (g == 0) ? 0ull : (km & ((1ull << (g * G)) - 1ull));
+    const size_t at = (size_t)((stg.tail + (unsigned long long)__popcll(below)) % (unsigned long long)(2 * W));
+    if (row_ok) {
+      const iv x = S.X[g][r];
+      double* dst = stg.box + (at * G + r) * 2;
+      dst[0] = x.lo;
+      dst[1] = x.nhi;
+    }
+    if (r == 0) stg.meta[at] = meta;
+  }
+  stg.tail += (unsigned long long)__popcll(km);
+  wave_lds_sync();
+}
+
 // ---------------------------------------------------------------------------
 // Grid barrier between levels.  Every wait is bounded: after timeout_ticks of
 // the 100 MHz device clock the barrier records IBB_ERR_TIMEOUT and returns, and
@@ -924,11 +1015,12 @@ __device__ __forceinline__ void grid_barrier(const SolveArgs& a, unsigned long l
   __threadfence();
 }
 
-// Resident waves per SIMD the register allocation aims for: three for one
-// system of up to 8 unknowns, whose n-sized scratch lets three fit in LDS.
+// Resident waves per SIMD the register allocation aims for.  Three would fit
+// in LDS for one system of up to 8 unknowns, but the two-stage step needs more
+// registers than three waves leave without spilling, except with 2 lanes.
 template <int G, bool MULTI>
 struct Occupancy {
-  static constexpr int waves = (!MULTI && G <= 8) ? 3 : 2;
+  static constexpr int waves = (!MULTI && G == 2) ? 3 : 2;
 };
 
 template <int G, bool MULTI>
@@ -954,6 +1046,12 @@ solve_kernel(SolveArgs a) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) sc.s[i] = 0;
   unsigned long long processed = 0, target = 0;
+  Stage stg;
+  {
+    const size_t wave = (size_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    stg.box = a.stage_box ? a.stage_box + wave * (size_t)(2 * W * G * 2) : nullptr;
+    stg.meta = a.stage_meta ? a.stage_meta + wave * (size_t)(2 * W) : nullptr;
+  }
   const int lane = __lane_id();
   Ctrl* c = a.ctrl;
   for (int level = a.level0;; ++level) {
@@ -988,8 +1086,21 @@ solve_kernel(SolveArgs a) {
       unsigned long long base = 0;
       if (lane == 0) base = atomicAdd(&c->claim[level % 3], (unsigned long long)W);
       base = __shfl(base, 0, 64);
-      if (base >= cnt) break;
-      step_tile<G, MULTI>(a, T, *S, J, (long long)base, (long long)cnt, cur, level, next_count, sc);
+      const bool more = base < cnt;
+      if (MULTI) {
+        if (!more) break;
+        step_tile<G, MULTI>(a, T, *S, J, (long long)base, (long long)cnt, cur, level, next_count, sc);
+        continue;
+      }
+      if (more) screen_tile<G, false>(a, T, *S, (long long)base, (long long)cnt, cur, sc, 0, false, nullptr, stg);
+      // step the screened boxes W at a time; at the end of the level, all of them
+      for (;;) {
+        const unsigned long long avail = stg.tail - stg.head;
+        if (avail == 0 || (more && avail < (unsigned long long)W)) break;
+        step_tile<G, false, false, true>(a, T, *S, J, 0, 0, cur, level, next_count, sc, 0, false, nullptr, &stg);
+        stg.head += avail < (unsigned long long)W ? avail : (unsigned long long)W;
+      }
+      if (!more) break;
     }
     grid_barrier(a, target);
   }
@@ -1033,8 +1144,15 @@ queue_kernel(SolveArgs a) {
   const int r = lane % G;
   Ctrl* c = a.ctrl;
   const unsigned long long qmask = (unsigned long long)a.front_cap - 1ull;
+  constexpr int W = 64 / G;
   long long slot = -1;  // this group's ring item (uniform over the group)
   QueueLocal ql;
+  Stage stg;
+  {
+    const size_t wave = (size_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    stg.box = a.stage_box + wave * (size_t)(2 * W * G * 2);
+    stg.meta = a.stage_meta + wave * (size_t)(2 * W);
+  }
   for (;;) {
     // groups without an item claim the next ones, one atomic per wave
     const uint64_t needm = __ballot(slot < 0 && r == 0);
@@ -1048,13 +1166,18 @@ queue_kernel(SolveArgs a) {
     // wait until some group's box is published, or the search is over
     bool full = false;
     bool stop = false;
+    bool screen = false;  // false: nothing published yet, step what the stage holds
     const long long t0 = wall_clock64();
     for (;;) {
       unsigned long long v = 0;
       if (r == 0) v = __hip_atomic_load(&a.qseq[(unsigned long long)slot & qmask], __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
       full = __shfl(v, g * G, 64) == (unsigned long long)slot + 1ull;
-      if (__ballot(full) != 0) break;
+      if (__ballot(full) != 0) {
+        screen = true;
+        break;
+      }
+      if (stg.tail > stg.head) break;
       int st = 0;
       unsigned long long pend = 1;
       if (lane == 0) {
@@ -1081,10 +1204,19 @@ queue_kernel(SolveArgs a) {
       __builtin_amdgcn_s_sleep(1);
     }
     if (stop) break;
-    // the published boxes are read after this point
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    step_tile<G, false, true>(a, T, *S, J, 0, 0, 0, 0, nullptr, sc, slot, full, &ql);
-    if (full) slot = -1;
+    if (screen) {
+      // the published boxes are read after this point
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      screen_tile<G, true>(a, T, *S, 0, 0, 0, sc, slot, full, &ql, stg);
+      if (full) slot = -1;
+    }
+    // step the screened boxes W at a time, or all of them when none was new
+    for (;;) {
+      const unsigned long long avail = stg.tail - stg.head;
+      if (avail == 0 || (screen && avail < (unsigned long long)W)) break;
+      step_tile<G, false, true, true>(a, T, *S, J, 0, 0, 0, 0, nullptr, sc, 0, false, &ql, &stg);
+      stg.head += avail < (unsigned long long)W ? avail : (unsigned long long)W;
+    }
   }
   if (lane == 0) {
 #pragma unroll

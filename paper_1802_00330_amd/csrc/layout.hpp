@@ -9,6 +9,7 @@ namespace ibb {
 constexpr int kMaxN = 16;
 constexpr int kBlock = 256;  // threads per workgroup (4 waves of 64)
 constexpr int kInfoLen = 16;
+constexpr int kStageWaves = 256 * 32;  // waves a persistent launch may have (CUs x waves per CU)
 
 // Compiled system, one contiguous blob of 8-byte words in device memory:
 //   [0, 16)           SysDesc
@@ -92,6 +93,10 @@ struct SolveArgs {
   // work-queue search: front[0]/meta[0] form a ring of front_cap (a power of
   // two) slots; qseq[s] = t: slot free for item t, t + 1: slot holds item t
   unsigned long long* qseq;
+  // one system: per wave, a ring of 2W screened boxes ([2W][G][2] doubles and
+  // [2W] records), indexed by the wave's global number
+  double* stage_box;
+  uint32_t* stage_meta;
   int slot_out_cap;  // > 0: each system emits into its own region of this many boxes
   unsigned long long* slot_out_count;  // [B] boxes emitted per system (regions)
   unsigned long long* pending_sys;     // [B] boxes per system still to step (or null)
