@@ -206,6 +206,7 @@ struct Scratch {
   iv Fc[W][G + 1];     // F at the expansion point
   iv Xc[W][G + 1];     // expansion point as degenerate intervals
   float row[W][G + 1]; // broadcast buffer of the single-precision solver
+  unsigned long long cnt[8];  // the wave's tree counters
 };
 
 // The interval Jacobian of the W boxes follows the Scratch block: box g, row
@@ -230,8 +231,25 @@ struct JView {
 // which the kernels leave at round-to-nearest-even.
 __device__ __forceinline__ float narrow_rn(double x) { return (float)x; }
 
+// The eight tree counters of a wave, kept in the wave's LDS scratch rather
+// than in registers (the search kernels are register-bound): added to by the
+// wave's first active lane, flushed to the control block when the wave ends.
 struct StepCounters {
-  unsigned long long s[8];
+  unsigned long long* s;
+  __device__ __forceinline__ void add(int k, unsigned long long v) const {
+    if (v && __lane_id() == __ffsll((long long)__ballot(1)) - 1) atomicAdd(&s[k], v);
+  }
+  __device__ __forceinline__ void clear() const {
+    if (__lane_id() < 8) s[__lane_id()] = 0ull;
+    wave_lds_sync();
+  }
+  __device__ __forceinline__ void flush(unsigned long long* stats) const {
+    wave_lds_sync();
+    if (__lane_id() < 8) {
+      const unsigned long long v = s[__lane_id()];
+      if (v) atomicAdd(&stats[__lane_id()], v);
+    }
+  }
 };
 
 enum : int { kProcessed = 0, kExclEval, kExclHs, kHsSkipped, kRecontract, kBisected, kEmitU, kEmitUnd };
@@ -401,7 +419,7 @@ template <int G, bool MULTI, bool QUEUE = false, bool STAGED = false>
 __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, Scratch<G>& S, const JView J,
                           long long base,
                           long long cnt, int cur, int level, unsigned long long* next_count,
-                          StepCounters& sc, long long qslot = 0, bool qvalid = false,
+                          const StepCounters& sc, long long qslot = 0, bool qvalid = false,
                           QueueLocal* ql = nullptr, Stage* stg = nullptr) {
   const int lane = __lane_id();
   const int g = lane / G;
@@ -809,15 +827,15 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
     }
   }
   if (!STAGED) {
-    sc.s[kProcessed] += __popcll(__ballot(leader));
-    sc.s[kExclEval] += __popcll(__ballot(leader && excluded));
+    sc.add(kProcessed, (unsigned long long)(__popcll(__ballot(leader))));
+    sc.add(kExclEval, (unsigned long long)(__popcll(__ballot(leader && excluded))));
   }
-  sc.s[kExclHs] += __popcll(__ballot(leader && hs_empty));
-  sc.s[kHsSkipped] += __popcll(__ballot(leader && active && !run));
-  sc.s[kRecontract] += __popcll(__ballot(leader && kind == 1));
-  sc.s[kBisected] += __popcll(__ballot(leader && (kind == 2 || kind == 3)));
-  sc.s[kEmitU] += __popcll(__ballot(leader && emit && tag == 1));
-  sc.s[kEmitUnd] += __popcll(__ballot(leader && emit && tag == 0));
+  sc.add(kExclHs, (unsigned long long)(__popcll(__ballot(leader && hs_empty))));
+  sc.add(kHsSkipped, (unsigned long long)(__popcll(__ballot(leader && active && !run))));
+  sc.add(kRecontract, (unsigned long long)(__popcll(__ballot(leader && kind == 1))));
+  sc.add(kBisected, (unsigned long long)(__popcll(__ballot(leader && (kind == 2 || kind == 3)))));
+  sc.add(kEmitU, (unsigned long long)(__popcll(__ballot(leader && emit && tag == 1))));
+  sc.add(kEmitUnd, (unsigned long long)(__popcll(__ballot(leader && emit && tag == 0))));
 
   // ---- compaction: one atomic per wave for the pushes, one for the emits
   const unsigned my_push = (r == 0) ? (unsigned)n_push : 0u;
@@ -937,7 +955,7 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
 // contraction because its box was excluded.
 template <int G, bool QUEUE>
 __device__ __forceinline__ void screen_tile(const SolveArgs& a, const LTable& T, Scratch<G>& S, long long base,
-                                            long long cnt, int cur, StepCounters& sc, long long qslot, bool qvalid,
+                                            long long cnt, int cur, const StepCounters& sc, long long qslot, bool qvalid,
                                             QueueLocal* ql, Stage& stg) {
   constexpr int W = 64 / G;
   const int lane = __lane_id();
@@ -968,9 +986,9 @@ __device__ __forceinline__ void screen_tile(const SolveArgs& a, const LTable& T,
   }
   const bool excluded = group_bits<G>(__ballot(excl_row), g) != 0;
   const bool leader = valid && r == 0;
-  sc.s[kProcessed] += __popcll(__ballot(leader));
+  sc.add(kProcessed, (unsigned long long)(__popcll(__ballot(leader))));
   const unsigned n_excl = (unsigned)__popcll(__ballot(leader && excluded));
-  sc.s[kExclEval] += n_excl;
+  sc.add(kExclEval, (unsigned long long)(n_excl));
   if (QUEUE) ql->pend -= (long long)n_excl;  // stepped boxes without children
   // survivors into the staging ring, in group order
   const bool keep = valid && !excluded;
@@ -1015,12 +1033,12 @@ __device__ __forceinline__ void grid_barrier(const SolveArgs& a, unsigned long l
   __threadfence();
 }
 
-// Resident waves per SIMD the register allocation aims for.  Three would fit
-// in LDS for one system of up to 8 unknowns, but the two-stage step needs more
-// registers than three waves leave without spilling, except with 2 lanes.
+// Resident waves per SIMD the register allocation aims for: three for one
+// system of up to 8 unknowns (its n-sized LDS scratch lets three workgroups of
+// four waves fit a CU), two otherwise (LDS admits no more).
 template <int G, bool MULTI>
 struct Occupancy {
-  static constexpr int waves = (!MULTI && G == 2) ? 3 : 2;
+  static constexpr int waves = (!MULTI && G <= 8) ? 3 : 2;
 };
 
 template <int G, bool MULTI>
@@ -1036,19 +1054,20 @@ solve_kernel(SolveArgs a) {
     table_bytes = align16(table_lds_bytes(d->n, d->T, d->TD));
   }
   const int jn = MULTI ? G : reinterpret_cast<const SysDesc*>(a.blob)->n;
-  char* const wave_base = smem + table_bytes + (threadIdx.x / 64) * wave_scratch_bytes<G>(jn, a.jrs);
+  // the wave's number within the workgroup, as a uniform (scalar) value
+  const int wave_in_block = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+  char* const wave_base = smem + table_bytes + (size_t)wave_in_block * wave_scratch_bytes<G>(jn, a.jrs);
   Scratch<G>* S = reinterpret_cast<Scratch<G>*>(wave_base);
   const JView J{reinterpret_cast<iv*>(wave_base + ((sizeof(Scratch<G>) + 15) / 16) * 16), jn * a.jrs + 1, a.jrs};
   __syncthreads();
 
   constexpr int W = 64 / G;
-  StepCounters sc;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) sc.s[i] = 0;
+  const StepCounters sc{S->cnt};
+  sc.clear();
   unsigned long long processed = 0, target = 0;
   Stage stg;
   {
-    const size_t wave = (size_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const size_t wave = (size_t)blockIdx.x * (blockDim.x / 64) + (size_t)wave_in_block;
     stg.box = a.stage_box ? a.stage_box + wave * (size_t)(2 * W * G * 2) : nullptr;
     stg.meta = a.stage_meta ? a.stage_meta + wave * (size_t)(2 * W) : nullptr;
   }
@@ -1104,11 +1123,7 @@ solve_kernel(SolveArgs a) {
     }
     grid_barrier(a, target);
   }
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (sc.s[i]) atomicAdd(&c->stats[i], sc.s[i]);
-  }
+  sc.flush(c->stats);
 }
 
 // ---------------------------------------------------------------------------
@@ -1131,14 +1146,15 @@ queue_kernel(SolveArgs a) {
   const LTable T = stage_table(a.blob, smem);
   const size_t table_bytes = align16(table_lds_bytes(d->n, d->T, d->TD));
   const int jn = d->n;
-  char* const wave_base = smem + table_bytes + (threadIdx.x / 64) * wave_scratch_bytes<G>(jn, a.jrs);
+  // the wave's number within the workgroup, as a uniform (scalar) value
+  const int wave_in_block = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+  char* const wave_base = smem + table_bytes + (size_t)wave_in_block * wave_scratch_bytes<G>(jn, a.jrs);
   Scratch<G>* S = reinterpret_cast<Scratch<G>*>(wave_base);
   const JView J{reinterpret_cast<iv*>(wave_base + ((sizeof(Scratch<G>) + 15) / 16) * 16), jn * a.jrs + 1, a.jrs};
   __syncthreads();
 
-  StepCounters sc;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) sc.s[i] = 0;
+  const StepCounters sc{S->cnt};
+  sc.clear();
   const int lane = __lane_id();
   const int g = lane / G;
   const int r = lane % G;
@@ -1149,7 +1165,7 @@ queue_kernel(SolveArgs a) {
   QueueLocal ql;
   Stage stg;
   {
-    const size_t wave = (size_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const size_t wave = (size_t)blockIdx.x * (blockDim.x / 64) + (size_t)wave_in_block;
     stg.box = a.stage_box + wave * (size_t)(2 * W * G * 2);
     stg.meta = a.stage_meta + wave * (size_t)(2 * W);
   }
@@ -1218,10 +1234,8 @@ queue_kernel(SolveArgs a) {
       stg.head += avail < (unsigned long long)W ? avail : (unsigned long long)W;
     }
   }
+  sc.flush(c->stats);
   if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (sc.s[i]) atomicAdd(&c->stats[i], sc.s[i]);
     if (ql.run_count && ql.run_depth < (unsigned)a.level_cap)
       atomicAdd(reinterpret_cast<unsigned long long*>(&a.level_sizes[ql.run_depth]), ql.run_count);
     if (ql.depth_max) atomicMax(&c->levels, (unsigned long long)ql.depth_max);
