@@ -249,6 +249,7 @@ struct ibb_ctx {
   std::vector<long long> last_levels;
   void* bws = nullptr;  // batch workspace
   size_t bws_bytes = 0;
+  long long batch_fcap = 0;  // frontier capacity the last batch needed
   // schedule autotuner: best kernel time per (n, T, TD, split mode) and
   // schedule, and the shape / schedule of the launch ev0..ev1 last bracketed
   std::map<std::tuple<int, int, int, int>, std::array<float, 2>> tune;
@@ -822,8 +823,11 @@ extern "C" int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* system
     for (int b = 0; b <= B; ++b) out_off[b] = 0;
     return IBB_OK;
   }
-  // capacities sized for the batch up front: an overflow re-runs the whole batch
-  long long fcap = 1LL << 22, ocap = std::max<long long>(1LL << 15, 16LL * B);
+  // capacities sized for the batch up front (an overflow re-runs the whole
+  // batch): large batches start at 16 M boxes per level, and a capacity a
+  // previous batch needed is reused
+  long long fcap = std::max<long long>({1LL << 22, B >= 1024 ? 1LL << 24 : 0LL, ctx->batch_fcap});
+  long long ocap = std::max<long long>(1LL << 15, 16LL * B);
   hipStream_t s = ctx->stream;
   for (int attempt = 0; attempt < 10; ++attempt) {
     const BatchLayout L = batch_layout(B, h.words, fcap, ocap);
@@ -850,6 +854,7 @@ extern "C" int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* system
       ocap = grow_o;
       continue;
     }
+    ctx->batch_fcap = std::max(ctx->batch_fcap, fcap);
     return IBB_OK;
   }
   return IBB_ERR_NO_MEMORY;
@@ -926,7 +931,7 @@ extern "C" int ibb_batch_plan_create(ibb_ctx* ctx, int32_t B, const ibb_system* 
     p->stream = nullptr;
     st = IBB_ERR_DEVICE;
   }
-  p->fcap = 1LL << 22;
+  p->fcap = std::max<long long>({1LL << 22, B >= 1024 ? 1LL << 24 : 0LL, ctx->batch_fcap});
   p->ocap = std::max<long long>(1LL << 15, 16LL * B);
   if (!st && p->h.any) st = plan_build(p);
   if (st) {
