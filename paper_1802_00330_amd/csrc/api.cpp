@@ -307,8 +307,10 @@ int resident_per_cu(ibb_ctx* ctx, const void* fn, int threads, size_t lds) {
 
 // Launch geometry of a persistent kernel: waves per block, LDS, grid and the
 // row stride of the Jacobian scratch.  jn is the Jacobian dimension the
-// kernel sizes its scratch for (n for one system, G for a batch); the row
-// stride is jn + 1 unless the padding would cost a resident workgroup.
+// kernel sizes its scratch for (n for one system, the largest member n for a
+// batch).  Every block holds its own copy of the table, so the choice is the
+// (row stride, waves per block) pair with the most resident waves per CU; on
+// a tie, the padded row stride and then the larger block.
 struct Geometry {
   int waves = 0, blocks = 0, jrs = 0;
   size_t lds = 0;
@@ -319,18 +321,18 @@ int persistent_geometry(ibb_ctx* ctx, const void* fn, size_t table_bytes, int G,
   int best_per_cu = 0;
   for (int rs : {jn + 1, jn}) {
     const size_t per_wave = scratch_bytes(G, jn, rs);
-    int waves = 4;
-    while (waves > 1 && table_bytes + per_wave * waves > ctx->max_lds_block) --waves;
-    const size_t lds = table_bytes + per_wave * waves;
-    if (lds > ctx->max_lds_block) continue;
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-      return IBB_ERR_DEVICE;
-    const int per_cu = resident_per_cu(ctx, fn, 64 * waves, lds);
-    if (per_cu * waves > best_per_cu * best.waves) {
-      best_per_cu = per_cu;
-      best.waves = waves;
-      best.lds = lds;
-      best.jrs = rs;
+    for (int waves = 4; waves >= 1; --waves) {
+      const size_t lds = table_bytes + per_wave * waves;
+      if (lds > ctx->max_lds_block) continue;
+      if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return IBB_ERR_DEVICE;
+      const int per_cu = resident_per_cu(ctx, fn, 64 * waves, lds);
+      if (per_cu * waves > best_per_cu * best.waves) {
+        best_per_cu = per_cu;
+        best.waves = waves;
+        best.lds = lds;
+        best.jrs = rs;
+      }
     }
   }
   if (best_per_cu < 1) return IBB_ERR_UNSUPPORTED;
@@ -390,6 +392,7 @@ int launch_search(ibb_ctx* ctx, const Compiled& c, const ibb_params* p, char* ws
   }
   a.nblocks = geo.blocks;
   a.jrs = geo.jrs;
+  a.jn = n;
   void* args[] = {&a};
   ctx->tune_pending = false;  // ev0 / ev1 now bracket this launch
   hipEventRecord(ctx->ev0, s);
@@ -577,6 +580,7 @@ struct BatchHost {
   std::vector<double> lo16, hi16;
   std::vector<int> bucket_list;
   int bucket_start[5] = {0, 0, 0, 0, 0};
+  int bucket_jn[4] = {0, 0, 0, 0};  // largest member n per bucket
   bool any = false;
 };
 
@@ -629,6 +633,8 @@ int batch_prepare(int B, const ibb_system* systems, const double* lo, const doub
   for (int q = 0; q < 4; ++q) {
     h.bucket_start[q] = (int)h.bucket_list.size();
     h.bucket_list.insert(h.bucket_list.end(), buckets[q].begin(), buckets[q].end());
+    h.bucket_jn[q] = 0;
+    for (int b : buckets[q]) h.bucket_jn[q] = std::max(h.bucket_jn[q], h.nsys[b]);
   }
   h.bucket_start[4] = (int)h.bucket_list.size();
   return IBB_OK;
@@ -705,10 +711,11 @@ int batch_enqueue(ibb_ctx* ctx, const BatchHost& h, char* w, const BatchLayout& 
     a.B = B;
     const void* fn = solve_kernel_ptr(G, true);
     Geometry geo;
-    const int st = persistent_geometry(ctx, fn, 0, G, G, &geo);
+    const int st = persistent_geometry(ctx, fn, 0, G, h.bucket_jn[q], &geo);
     if (st) return st;
     a.nblocks = geo.blocks;
     a.jrs = geo.jrs;
+    a.jn = h.bucket_jn[q];
     void* args[] = {&a};
     if (hipLaunchCooperativeKernel(fn, dim3(geo.blocks), dim3(64 * geo.waves), args, (unsigned)geo.lds, s) !=
         hipSuccess)
@@ -1688,12 +1695,16 @@ int ibb_server_step(ibb_server* sv) {
     a.stats_sys = sv->stats_sys;
     a.pending_sys = sv->pending;
     a.B = S;
+    // the Jacobian scratch fits the largest system of the bucket's active slots
+    int jn = 0;
+    for (int slot : b.slots) jn = std::max(jn, sv->by_slot[slot]->comp.n);
     const void* fn = solve_kernel_ptr(b.G, true);
     Geometry geo;
-    const int st = persistent_geometry(ctx, fn, 0, b.G, b.G, &geo);
+    const int st = persistent_geometry(ctx, fn, 0, b.G, jn, &geo);
     if (st) return st;
     a.nblocks = geo.blocks;
     a.jrs = geo.jrs;
+    a.jn = jn;
     void* args[] = {&a};
     if (hipLaunchCooperativeKernel(fn, dim3(geo.blocks), dim3(64 * geo.waves), args, (unsigned)geo.lds, s) !=
         hipSuccess)

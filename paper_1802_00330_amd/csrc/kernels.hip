@@ -211,10 +211,11 @@ struct Scratch {
 
 // The interval Jacobian of the W boxes follows the Scratch block: box g, row
 // r, column k at g * (jn * rs + 1) + r * rs + k, with jn = n for one system
-// (the area shrinks with n, which raises the number of resident waves), jn =
-// G for batches of systems of different sizes, and a row stride rs of jn or
+// and the largest n among the members for batches of systems of different
+// sizes (the area shrinks with jn, which raises the number of resident
+// waves; every access has r, k < n <= jn), and a row stride rs of jn or
 // jn + 1 (padding spreads the rows of a box over the LDS banks; the host drops
-// it when it would cost a resident workgroup).
+// it when it would cost resident waves).
 template <int G>
 __host__ __device__ constexpr size_t wave_scratch_bytes(int jn, int rs) {
   return ((sizeof(Scratch<G>) + 15) / 16) * 16 + (size_t)(64 / G) * (jn * rs + 1) * sizeof(iv);
@@ -1053,7 +1054,7 @@ solve_kernel(SolveArgs a) {
     T = stage_table(a.blob, smem);
     table_bytes = align16(table_lds_bytes(d->n, d->T, d->TD));
   }
-  const int jn = MULTI ? G : reinterpret_cast<const SysDesc*>(a.blob)->n;
+  const int jn = MULTI ? a.jn : reinterpret_cast<const SysDesc*>(a.blob)->n;
   // the wave's number within the workgroup, as a uniform (scalar) value
   const int wave_in_block = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
   char* const wave_base = smem + table_bytes + (size_t)wave_in_block * wave_scratch_bytes<G>(jn, a.jrs);
