@@ -168,6 +168,56 @@ int ibb_batch_plan_run(ibb_batch_plan* plan, double* out_lo, double* out_hi, uin
                        int64_t cap, int64_t* out_off, int32_t* status, ibb_stats* stats);
 void ibb_batch_plan_destroy(ibb_batch_plan* plan);
 
+/* ---- batch launch configuration and its autotuner ----
+ * Members of a batch fall into four lane-count classes by size: class 0
+ * (n <= 2), 1 (n <= 4), 2 (n <= 8), 3 (n <= 16).  A context holds one launch
+ * configuration per class, which ibb_solve_batch and ibb_batch_plan_create
+ * apply to the members of that class (a plan keeps the configuration it was
+ * created with):
+ *   lanes            lanes per box: 2 << class (the default) or a larger power
+ *                    of two up to 16; members then share the persistent launch
+ *                    of that lane count, whose configuration (the other fields)
+ *                    is the one of the class with that lane count;
+ *   tiles_per_claim  tiles a wave takes per atomic claim of the level's
+ *                    frontier (1 .. 16, default 1);
+ *   blocks_per_cu    resident workgroups per CU of that launch (0, the
+ *                    default, as many as registers and LDS allow; larger
+ *                    values are clamped to that);
+ *   tuned, ms        set by ibb_batch_tune: 1 and the measured device time of
+ *                    the class's sample with this configuration (else 0, 0).
+ * Each box's fate depends on the box alone, so results, counters and statuses
+ * are the same under every configuration (the batched analogue of the
+ * autotuner's schedule choice for one system). */
+typedef struct ibb_batch_config {
+  int32_t lanes;
+  int32_t tiles_per_claim;
+  int32_t blocks_per_cu;
+  int32_t tuned;
+  double ms;
+} ibb_batch_config;
+
+/* Current configuration of class cls (0..3) into *out.  IBB_ERR_INVALID_ARG
+ * for a bad class or null pointer. */
+int ibb_batch_get_config(ibb_ctx* ctx, int32_t cls, ibb_batch_config* out);
+
+/* Replace the configuration of class cls (tuned and ms are ignored and
+ * cleared).  IBB_ERR_INVALID_ARG unless lanes is a power of two with
+ * 2 << cls <= lanes <= 16, 1 <= tiles_per_claim <= 16 and blocks_per_cu >= 0. */
+int ibb_batch_set_config(ibb_ctx* ctx, int32_t cls, const ibb_batch_config* cfg);
+
+/* Autotuner: for every class with valid members among the B given systems
+ * (arguments as ibb_solve_batch), solves the class's first min(count, sample)
+ * members as a batch under each candidate configuration -- lanes per box
+ * {2 << cls, 4 << cls (up to 16)} x tiles per claim {1, 4} x workgroups per CU
+ * {all that fit, two thirds of them} -- timing the device work of each with
+ * HIP events, and keeps the fastest in the context (a candidate must beat the
+ * default configuration by 3 % to replace it).  The solves' results are
+ * discarded; every candidate must reproduce the default's counters and
+ * statuses exactly, else IBB_ERR_DEVICE.  sample >= 1.  Takes the device
+ * time of (candidates x sample) solves; blocks until done. */
+int ibb_batch_tune(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const double* lo, const double* hi,
+                   const ibb_params* params, int32_t sample);
+
 /* ---- serving: continuous batching of solves on one device ----
  * Requests are queued by ibb_server_submit (the system is copied).  Each call
  * of ibb_server_step (1) admits queued requests while a device slot is free

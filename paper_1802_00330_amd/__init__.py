@@ -36,7 +36,7 @@ EXPORTS = ("ibb_ctx_create", "ibb_ctx_destroy", "ibb_strerror", "ibb_params_defa
            "ibb_selftest_ops", "ibb_debug_step", "ibb_solve_batch", "ibb_server_config_default",
            "ibb_server_create", "ibb_server_destroy", "ibb_server_submit", "ibb_server_step", "ibb_server_poll",
            "ibb_server_cancel", "ibb_server_pending", "ibb_round", "ibb_batch_plan_create", "ibb_batch_plan_run",
-           "ibb_batch_plan_destroy")
+           "ibb_batch_plan_destroy", "ibb_batch_get_config", "ibb_batch_set_config", "ibb_batch_tune")
 
 
 class IbbSystem(C.Structure):
@@ -52,6 +52,15 @@ class IbbParams(C.Structure):
 class IbbServerConfig(C.Structure):
     _fields_ = [("max_slots", C.c_int32), ("frontier_cap", C.c_int64), ("reserve_per_solve", C.c_int64),
                 ("levels_per_quantum", C.c_int32), ("out_cap_per_solve", C.c_int32)]
+
+
+class IbbBatchConfig(C.Structure):
+    """Launch configuration of one lane-count class of batch members (ibb_batch_config)."""
+    _fields_ = [("lanes", C.c_int32), ("tiles_per_claim", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("tuned", C.c_int32), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class IbbStats(C.Structure):
@@ -112,6 +121,11 @@ def load_library(path: str = LIB_PATH):
     L.ibb_batch_plan_run.restype = C.c_int
     L.ibb_batch_plan_run.argtypes = [p, p, p, p, i64, p, p, p]
     L.ibb_batch_plan_destroy.restype, L.ibb_batch_plan_destroy.argtypes = None, [p]
+    L.ibb_batch_get_config.restype = C.c_int
+    L.ibb_batch_get_config.argtypes = [p, i32, C.POINTER(IbbBatchConfig)]
+    L.ibb_batch_set_config.restype = C.c_int
+    L.ibb_batch_set_config.argtypes = [p, i32, C.POINTER(IbbBatchConfig)]
+    L.ibb_batch_tune.restype, L.ibb_batch_tune.argtypes = C.c_int, [p, i32, p, p, p, p, i32]
     L.ibb_round.restype = C.c_int
     L.ibb_round.argtypes = [p, C.POINTER(IbbSystem), C.POINTER(IbbParams), i64, p, p, p, p, p, p, i64,
                             C.POINTER(C.c_int64), p, p, p, i64, C.POINTER(C.c_int64), C.POINTER(IbbStats)]
@@ -399,6 +413,33 @@ def ibb_solve_batch(ctx: Context, systems, params=None, cap: int = 1 << 16):
         return L.ibb_solve_batch(ctx.handle, int(len(systems)), arr, _ptr(lo), _ptr(hi), parr, *outs)
 
     return _batch_results(call, systems, cap, "ibb_solve_batch")
+
+
+def ibb_batch_get_config(ctx: Context, cls: int) -> IbbBatchConfig:
+    """The context's launch configuration of lane-count class cls (0..3)."""
+    c = IbbBatchConfig()
+    st = load_library().ibb_batch_get_config(ctx.handle, int(cls), C.byref(c))
+    if st != OK:
+        raise RuntimeError(f"ibb_batch_get_config: {ibb_strerror(st)}")
+    return c
+
+
+def ibb_batch_set_config(ctx: Context, cls: int, lanes: int, tiles_per_claim: int = 1, blocks_per_cu: int = 0):
+    """Force the launch configuration of lane-count class cls."""
+    c = IbbBatchConfig(int(lanes), int(tiles_per_claim), int(blocks_per_cu), 0, 0.0)
+    st = load_library().ibb_batch_set_config(ctx.handle, int(cls), C.byref(c))
+    if st != OK:
+        raise RuntimeError(f"ibb_batch_set_config: {ibb_strerror(st)}")
+
+
+def ibb_batch_tune(ctx: Context, systems, params=None, sample: int = 256):
+    """Autotune the batch launch configuration of each class present among the
+    systems (ibb_batch_tune); returns the four class configurations as dicts."""
+    refs, arr, lo, hi, parr = _batch_inputs(systems, params)
+    st = load_library().ibb_batch_tune(ctx.handle, int(len(systems)), arr, _ptr(lo), _ptr(hi), parr, int(sample))
+    if st != OK:
+        raise RuntimeError(f"ibb_batch_tune: {ibb_strerror(st)}")
+    return [ibb_batch_get_config(ctx, q).as_dict() for q in range(4)]
 
 
 class BatchPlan:

@@ -60,6 +60,9 @@ int lanes_for(int n) {
 
 inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Lane-count class of a power of two 2..16: 0..3.
+int lanes_class(int G) { return G == 2 ? 0 : G == 4 ? 1 : G == 8 ? 2 : 3; }
+
 // ---------------------------------------------------------------------------
 // Validation and compilation of a system into the device blob (layout.hpp).
 // ---------------------------------------------------------------------------
@@ -250,6 +253,8 @@ struct ibb_ctx {
   void* bws = nullptr;  // batch workspace
   size_t bws_bytes = 0;
   long long batch_fcap = 0;  // frontier capacity the last batch needed
+  // launch configuration of each lane-count class of batch members
+  ibb_batch_config batch_cfg[4] = {{2, 1, 0, 0, 0.0}, {4, 1, 0, 0, 0.0}, {8, 1, 0, 0, 0.0}, {16, 1, 0, 0, 0.0}};
   // schedule autotuner: best kernel time per (n, T, TD, split mode) and
   // schedule, and the shape / schedule of the launch ev0..ev1 last bracketed
   std::map<std::tuple<int, int, int, int>, std::array<float, 2>> tune;
@@ -581,11 +586,13 @@ struct BatchHost {
   std::vector<int> bucket_list;
   int bucket_start[5] = {0, 0, 0, 0, 0};
   int bucket_jn[4] = {0, 0, 0, 0};  // largest member n per bucket
+  int bucket_pop[4] = {1, 1, 1, 1};     // tiles per claim
+  int bucket_per_cu[4] = {0, 0, 0, 0};  // resident workgroups per CU (0 = all that fit)
   bool any = false;
 };
 
 int batch_prepare(int B, const ibb_system* systems, const double* lo, const double* hi, const ibb_params* params,
-                  int32_t* status, BatchHost& h) {
+                  const ibb_batch_config* cfg, int32_t* status, BatchHost& h) {
   h.B = B;
   std::vector<Compiled> comp((size_t)B);
   h.boff.assign((size_t)B, 0);
@@ -608,8 +615,8 @@ int batch_prepare(int B, const ibb_system* systems, const double* lo, const doub
     h.nsys[b] = comp[b].n;
     const ibb_params& p = params[b];
     h.sp[b] = SysParams{p.tol, p.recontract_ratio, p.hs_max_width, p.max_boxes, p.split_mode, p.max_recontract};
-    const int G = comp[b].G;
-    buckets[G == 2 ? 0 : G == 4 ? 1 : G == 8 ? 2 : 3].push_back(b);
+    // the member runs with the lane count its class is configured for
+    buckets[lanes_class(cfg[lanes_class(comp[b].G)].lanes)].push_back(b);
   }
   h.any = first_valid >= 0;
   if (!h.any) return IBB_OK;
@@ -635,6 +642,8 @@ int batch_prepare(int B, const ibb_system* systems, const double* lo, const doub
     h.bucket_list.insert(h.bucket_list.end(), buckets[q].begin(), buckets[q].end());
     h.bucket_jn[q] = 0;
     for (int b : buckets[q]) h.bucket_jn[q] = std::max(h.bucket_jn[q], h.nsys[b]);
+    h.bucket_pop[q] = cfg[q].tiles_per_claim;
+    h.bucket_per_cu[q] = cfg[q].blocks_per_cu;
   }
   h.bucket_start[4] = (int)h.bucket_list.size();
   return IBB_OK;
@@ -713,9 +722,11 @@ int batch_enqueue(ibb_ctx* ctx, const BatchHost& h, char* w, const BatchLayout& 
     Geometry geo;
     const int st = persistent_geometry(ctx, fn, 0, G, h.bucket_jn[q], &geo);
     if (st) return st;
+    if (h.bucket_per_cu[q] > 0) geo.blocks = std::min(geo.blocks, h.bucket_per_cu[q] * ctx->num_cu);
     a.nblocks = geo.blocks;
     a.jrs = geo.jrs;
     a.jn = h.bucket_jn[q];
+    a.tiles_per_claim = h.bucket_pop[q];
     void* args[] = {&a};
     if (hipLaunchCooperativeKernel(fn, dim3(geo.blocks), dim3(64 * geo.waves), args, (unsigned)geo.lds, s) !=
         hipSuccess)
@@ -816,15 +827,18 @@ bool batch_outputs_ok(int64_t cap, const double* out_lo, const double* out_hi, c
 
 }  // namespace
 
-extern "C" int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const double* lo,
-                               const double* hi, const ibb_params* params, double* out_lo, double* out_hi,
-                               uint8_t* out_tag, int64_t cap, int64_t* out_off, int32_t* status,
-                               ibb_stats* stats) {
-  if (!batch_args_ok(ctx, B, systems, lo, hi, params) || !batch_outputs_ok(cap, out_lo, out_hi, out_tag, out_off, status))
-    return IBB_ERR_INVALID_ARG;
+namespace {
+
+// One eager batch solve under the launch configurations cfg[4]; *ms (if not
+// null) receives the device time of the batch's device work.
+int solve_batch_with(ibb_ctx* ctx, const ibb_batch_config* cfg, int32_t B, const ibb_system* systems,
+                     const double* lo, const double* hi, const ibb_params* params, double* out_lo, double* out_hi,
+                     uint8_t* out_tag, int64_t cap, int64_t* out_off, int32_t* status, ibb_stats* stats,
+                     float* ms) {
   if (hipSetDevice(ctx->device) != hipSuccess) return IBB_ERR_DEVICE;
+  if (ms) *ms = 0.0f;
   BatchHost h;
-  int st = batch_prepare(B, systems, lo, hi, params, status, h);
+  int st = batch_prepare(B, systems, lo, hi, params, cfg, status, h);
   if (st) return st;
   if (!h.any) {
     for (int b = 0; b <= B; ++b) out_off[b] = 0;
@@ -862,9 +876,140 @@ extern "C" int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* system
       continue;
     }
     ctx->batch_fcap = std::max(ctx->batch_fcap, fcap);
+    if (ms && hipEventElapsedTime(ms, ctx->ev0, ctx->ev1) != hipSuccess) return IBB_ERR_DEVICE;
     return IBB_OK;
   }
   return IBB_ERR_NO_MEMORY;
+}
+
+}  // namespace
+
+extern "C" int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const double* lo,
+                               const double* hi, const ibb_params* params, double* out_lo, double* out_hi,
+                               uint8_t* out_tag, int64_t cap, int64_t* out_off, int32_t* status,
+                               ibb_stats* stats) {
+  if (!batch_args_ok(ctx, B, systems, lo, hi, params) || !batch_outputs_ok(cap, out_lo, out_hi, out_tag, out_off, status))
+    return IBB_ERR_INVALID_ARG;
+  return solve_batch_with(ctx, ctx->batch_cfg, B, systems, lo, hi, params, out_lo, out_hi, out_tag, cap, out_off,
+                          status, stats, nullptr);
+}
+
+extern "C" int ibb_batch_get_config(ibb_ctx* ctx, int32_t cls, ibb_batch_config* out) {
+  if (!ctx || !out || cls < 0 || cls > 3) return IBB_ERR_INVALID_ARG;
+  *out = ctx->batch_cfg[cls];
+  return IBB_OK;
+}
+
+namespace {
+bool batch_config_ok(int32_t cls, const ibb_batch_config& c) {
+  const int L = c.lanes;
+  return L >= (2 << cls) && L <= 16 && (L & (L - 1)) == 0 && c.tiles_per_claim >= 1 && c.tiles_per_claim <= 16 &&
+         c.blocks_per_cu >= 0;
+}
+}  // namespace
+
+extern "C" int ibb_batch_set_config(ibb_ctx* ctx, int32_t cls, const ibb_batch_config* cfg) {
+  if (!ctx || !cfg || cls < 0 || cls > 3 || !batch_config_ok(cls, *cfg)) return IBB_ERR_INVALID_ARG;
+  ctx->batch_cfg[cls] = ibb_batch_config{cfg->lanes, cfg->tiles_per_claim, cfg->blocks_per_cu, 0, 0.0};
+  return IBB_OK;
+}
+
+extern "C" int ibb_batch_tune(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const double* lo, const double* hi,
+                              const ibb_params* params, int32_t sample) {
+  if (!batch_args_ok(ctx, B, systems, lo, hi, params) || sample < 1) return IBB_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return IBB_ERR_DEVICE;
+  std::vector<int> members[4];
+  for (int b = 0; b < B; ++b)
+    if (validate(&systems[b], lo + (size_t)b * kMaxN, hi + (size_t)b * kMaxN, &params[b]) == IBB_OK)
+      members[lanes_class(lanes_for(systems[b].n))].push_back(b);
+  // wider classes first: a narrower class may move its members into the
+  // launch of a wider one, whose configuration is then already chosen
+  for (int q = 3; q >= 0; --q) {
+    if (members[q].empty()) continue;
+    const int m = (int)std::min<size_t>(members[q].size(), (size_t)sample);
+    std::vector<ibb_system> ss((size_t)m);
+    std::vector<ibb_params> ps((size_t)m);
+    std::vector<double> ls((size_t)m * kMaxN), hs((size_t)m * kMaxN);
+    int jn = 0;
+    for (int i = 0; i < m; ++i) {
+      const int b = members[q][(size_t)i];
+      ss[(size_t)i] = systems[b];
+      ps[(size_t)i] = params[b];
+      std::memcpy(&ls[(size_t)i * kMaxN], lo + (size_t)b * kMaxN, sizeof(double) * kMaxN);
+      std::memcpy(&hs[(size_t)i * kMaxN], hi + (size_t)b * kMaxN, sizeof(double) * kMaxN);
+      jn = std::max(jn, systems[b].n);
+    }
+    const int G = 2 << q;
+    // workgroups per CU that fit the natural launch
+    Geometry geo;
+    int st = persistent_geometry(ctx, solve_kernel_ptr(G, true), 0, G, jn, &geo);
+    if (st) return st;
+    const int full = geo.blocks / ctx->num_cu;
+    const int part = std::max(1, (2 * full + 2) / 3);
+    std::vector<ibb_batch_config> cands;
+    const ibb_batch_config def{G, 1, 0, 0, 0.0};
+    cands.push_back(def);
+    for (int pop : {1, 4})
+      for (int pc : {0, part}) {
+        if (pop == 1 && pc == 0) continue;
+        if (pc == full) continue;
+        cands.push_back(ibb_batch_config{G, pop, pc, 0, 0.0});
+      }
+    if (G < 16) {
+      const ibb_batch_config& w = ctx->batch_cfg[q + 1];
+      cands.push_back(ibb_batch_config{2 * G, w.tiles_per_claim, w.blocks_per_cu, 0, 0.0});
+    }
+    // results of the sample solves (discarded; compared across candidates)
+    int64_t cap = std::max<int64_t>(1 << 12, 8LL * m);
+    std::vector<double> olo, ohi;
+    std::vector<uint8_t> otag;
+    std::vector<int64_t> off((size_t)m + 1);
+    std::vector<int32_t> stat((size_t)m), stat0((size_t)m);
+    std::vector<ibb_stats> sts((size_t)m), sts0((size_t)m);
+    std::vector<float> times(cands.size(), 0.0f);
+    for (size_t c = 0; c <= cands.size(); ++c) {
+      // run 0 warms the default launch up; runs 1.. time the candidates
+      const ibb_batch_config& cand = cands[c == 0 ? 0 : c - 1];
+      ibb_batch_config cfg[4] = {{2, 1, 0, 0, 0.0}, {4, 1, 0, 0, 0.0}, {8, 1, 0, 0, 0.0}, {16, 1, 0, 0, 0.0}};
+      cfg[q] = cand;
+      const int qe = lanes_class(cand.lanes);
+      if (qe != q) cfg[qe] = ibb_batch_config{cand.lanes, cand.tiles_per_claim, cand.blocks_per_cu, 0, 0.0};
+      float ms = 0.0f;
+      for (;;) {
+        olo.assign((size_t)cap * kMaxN, 0.0);
+        ohi.assign((size_t)cap * kMaxN, 0.0);
+        otag.assign((size_t)cap, 0);
+        st = solve_batch_with(ctx, cfg, m, ss.data(), ls.data(), hs.data(), ps.data(), olo.data(), ohi.data(),
+                              otag.data(), cap, off.data(), stat.data(), sts.data(), &ms);
+        if (st == IBB_ERR_OUTPUT_CAPACITY && off[(size_t)m] > cap) {
+          cap = off[(size_t)m];
+          continue;
+        }
+        break;
+      }
+      if (st) return st;
+      if (c == 0) {
+        stat0 = stat;
+        sts0 = sts;
+        continue;
+      }
+      // every configuration must reproduce the default's statuses and counters
+      for (int i = 0; i < m; ++i)
+        if (stat[(size_t)i] != stat0[(size_t)i] ||
+            std::memcmp(&sts[(size_t)i], &sts0[(size_t)i], sizeof(ibb_stats)) != 0)
+          return IBB_ERR_DEVICE;
+      times[c - 1] = ms;
+    }
+    size_t best = 0;
+    for (size_t c = 1; c < cands.size(); ++c)
+      if (times[c] < times[best]) best = c;
+    if (best != 0 && times[best] > 0.97f * times[0]) best = 0;
+    ibb_batch_config chosen = cands[best];
+    chosen.tuned = 1;
+    chosen.ms = (double)times[best];
+    ctx->batch_cfg[q] = chosen;
+  }
+  return IBB_OK;
 }
 
 // A batch prepared once and solved many times: inputs uploaded and the device
@@ -933,7 +1078,7 @@ extern "C" int ibb_batch_plan_create(ibb_ctx* ctx, int32_t B, const ibb_system* 
   if (!p) return IBB_ERR_NO_MEMORY;
   p->ctx = ctx;
   p->status0.assign((size_t)B, 0);
-  int st = batch_prepare(B, systems, lo, hi, params, p->status0.data(), p->h);
+  int st = batch_prepare(B, systems, lo, hi, params, ctx->batch_cfg, p->status0.data(), p->h);
   if (!st && hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess) {
     p->stream = nullptr;
     st = IBB_ERR_DEVICE;

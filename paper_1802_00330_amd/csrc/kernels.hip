@@ -1036,10 +1036,12 @@ __device__ __forceinline__ void grid_barrier(const SolveArgs& a, unsigned long l
 
 // Resident waves per SIMD the register allocation aims for: three for one
 // system of up to 8 unknowns (its n-sized LDS scratch lets three workgroups of
-// four waves fit a CU), two otherwise (LDS admits no more).
+// four waves fit a CU) and for batches (scratch sized for the largest member:
+// up to ten waves per CU at n = 12), two for one system of 9 to 16 unknowns
+// (its table and scratch admit no more).
 template <int G, bool MULTI>
 struct Occupancy {
-  static constexpr int waves = (!MULTI && G <= 8) ? 3 : 2;
+  static constexpr int waves = (MULTI || G <= 8) ? 3 : 2;
 };
 
 template <int G, bool MULTI>
@@ -1102,14 +1104,20 @@ solve_kernel(SolveArgs a) {
     }
     const int cur = level & 1;
     unsigned long long* next_count = &c->count[(level + 1) % 3];
+    // batches: a wave claims `pop` consecutive tiles per atomic
+    const int pop = (MULTI && a.tiles_per_claim > 1) ? a.tiles_per_claim : 1;
     for (;;) {
       unsigned long long base = 0;
-      if (lane == 0) base = atomicAdd(&c->claim[level % 3], (unsigned long long)W);
+      if (lane == 0) base = atomicAdd(&c->claim[level % 3], (unsigned long long)(W * pop));
       base = __shfl(base, 0, 64);
       const bool more = base < cnt;
       if (MULTI) {
         if (!more) break;
-        step_tile<G, MULTI>(a, T, *S, J, (long long)base, (long long)cnt, cur, level, next_count, sc);
+        for (int t = 0; t < pop; ++t) {
+          const unsigned long long tb = base + (unsigned long long)(t * W);
+          if (tb >= cnt) break;
+          step_tile<G, MULTI>(a, T, *S, J, (long long)tb, (long long)cnt, cur, level, next_count, sc);
+        }
         continue;
       }
       if (more) screen_tile<G, false>(a, T, *S, (long long)base, (long long)cnt, cur, sc, 0, false, nullptr, stg);

@@ -91,6 +91,7 @@ struct SolveArgs {
   int level0;      // index of the first level of this launch (continuing searches)
   int jrs;         // row stride (in intervals) of the per-box Jacobian in LDS
   int jn;          // rows of the per-box Jacobian in LDS (batches: the largest n among the members)
+  int tiles_per_claim;  // batches: tiles a wave claims per atomic (values below 1 act as 1)
   // work-queue search: front[0]/meta[0] form a ring of front_cap (a power of
   // two) slots; qseq[s] = t: slot free for item t, t + 1: slot holds item t
   unsigned long long* qseq;

@@ -89,3 +89,88 @@ def test_batch_plan_replays_equal_eager_and_oracle(gpu_ctx, oracle_lib):
             torch.cuda.synchronize()
     finally:
         plan.close()
+
+
+def _defaults(P, ctx):
+    for q in range(4):
+        P.ibb_batch_set_config(ctx, q, 2 << q)
+
+
+# forced launch configurations: (class, lanes, tiles per claim, workgroups per CU)
+_CONFIGS = {
+    "wider lanes, 4 tiles per claim, 1 workgroup per CU": [(0, 4, 4, 1), (1, 8, 4, 1), (2, 16, 4, 1), (3, 16, 4, 1)],
+    "16 lanes for all, 2 tiles per claim": [(0, 16, 2, 0), (1, 16, 2, 0), (2, 16, 2, 0), (3, 16, 2, 0)],
+    "natural lanes, 3 tiles per claim, 2 workgroups per CU": [(0, 2, 3, 2), (1, 4, 3, 2), (2, 8, 3, 2), (3, 16, 3, 2)],
+}
+
+
+@pytest.mark.parametrize("name", list(_CONFIGS))
+def test_batch_results_independent_of_launch_config(gpu_ctx, oracle_lib, name):
+    """Lanes per box, tiles per claim and workgroups per CU change how the
+    device schedules the boxes, never a box's fate: every member's boxes,
+    tags, counters and status equal the oracle's under each configuration."""
+    import paper_1802_00330_amd as P
+    systems = _mixed_systems()
+    bad = W.circle_line()
+    bad.coef[0] = float("inf")
+    systems = systems[:3] + [bad] + systems[3:]
+    ref = [oracle_lib.solve(s) if k != 3 else None for k, s in enumerate(systems)]
+    try:
+        for q, lanes, pop, pc in _CONFIGS[name]:
+            P.ibb_batch_set_config(gpu_ctx, q, lanes, pop, pc)
+        print(f"[batch-config] {name}", flush=True)
+        res = P.ibb_solve_batch(gpu_ctx, systems)
+        plan = P.BatchPlan(gpu_ctx, systems)
+        try:
+            replay = plan.run()
+        finally:
+            plan.close()
+    finally:
+        _defaults(P, gpu_ctx)
+    for k, (s, r, g) in enumerate(zip(systems, res, replay)):
+        if k == 3:
+            assert r.status == P.ERR_INVALID_ARG and g.status == P.ERR_INVALID_ARG
+            continue
+        assert_same(r, ref[k], f"{name}: {s.name}")
+        assert_same(g, ref[k], f"{name} (plan): {s.name}")
+
+
+def test_batch_tune_keeps_results(gpu_ctx, oracle_lib):
+    """The autotuner times candidate configurations on a sample of each class,
+    keeps a valid one per class present, and the tuned batch still equals the
+    oracle member by member."""
+    import paper_1802_00330_amd as P
+    systems = _mixed_systems()
+    ref = [oracle_lib.solve(s) for s in systems]
+    try:
+        cfgs = P.ibb_batch_tune(gpu_ctx, systems, sample=6)
+        print(f"[batch-tune] {cfgs}", flush=True)
+        present = {min(q for q in range(4) if s.n <= 2 << q) for s in systems}
+        for q, c in enumerate(cfgs):
+            if q in present:
+                assert c["tuned"] == 1 and c["ms"] > 0.0
+                assert c["lanes"] in (2 << q, 4 << q) and c["lanes"] <= 16
+                assert c["tiles_per_claim"] in (1, 4) and c["blocks_per_cu"] >= 0
+            else:
+                assert c["tuned"] == 0 and c["lanes"] == 2 << q
+        res = P.ibb_solve_batch(gpu_ctx, systems)
+    finally:
+        _defaults(P, gpu_ctx)
+    for s, r, o in zip(systems, res, ref):
+        assert_same(r, o, f"tuned: {s.name}")
+
+
+def test_batch_set_config_rejects_invalid(gpu_ctx):
+    import paper_1802_00330_amd as P
+    bad = [(0, 3, 1, 0), (1, 2, 1, 0), (2, 32, 1, 0), (3, 8, 1, 0), (0, 2, 0, 0), (0, 2, 17, 0), (0, 2, 1, -1),
+           (4, 16, 1, 0), (-1, 2, 1, 0)]
+    try:
+        for q, lanes, pop, pc in bad:
+            with pytest.raises(RuntimeError, match="invalid"):
+                P.ibb_batch_set_config(gpu_ctx, q, lanes, pop, pc)
+        P.ibb_batch_set_config(gpu_ctx, 1, 16, 16, 3)
+        c = P.ibb_batch_get_config(gpu_ctx, 1)
+        assert (c.lanes, c.tiles_per_claim, c.blocks_per_cu, c.tuned) == (16, 16, 3, 0)
+    finally:
+        _defaults(P, gpu_ctx)
+    assert P.ibb_batch_get_config(gpu_ctx, 1).lanes == 4
