@@ -61,6 +61,11 @@ def batched_leg(ctx, P, W, count, budget, plain_sample, log):
     log(f"[bench] batch: generated {count} systems in {time.perf_counter() - t:.1f} s")
     params = [P.make_params(s.tol, max_boxes=budget) for s in systems]
     P.ibb_solve_batch(ctx, systems[:64], params[:64])  # warm-up
+    # launch configuration per lane-count class, timed on a sample of each class
+    t = time.perf_counter()
+    tuned = P.ibb_batch_tune(ctx, systems, params, sample=128)
+    tune_s = time.perf_counter() - t
+    log(f"[bench] batch: autotuned in {tune_s:.1f} s: {tuned}")
     t = time.perf_counter()
     res = P.ibb_solve_batch(ctx, systems, params)
     dt = time.perf_counter() - t
@@ -92,6 +97,9 @@ def batched_leg(ctx, P, W, count, budget, plain_sample, log):
     same = all(a.status == b.status and a.stats == b.stats and np.array_equal(a.lo, b.lo)
                and np.array_equal(a.hi, b.hi) and np.array_equal(a.tag, b.tag) for a, b in zip(rres, res))
     return {"systems": count, "budget_nodes_per_system": budget, "completed": done,
+            "autotune": {"seconds": tune_s, "sample_per_class": 128,
+                         "classes": [{k: c[k] for k in ("lanes", "tiles_per_claim", "blocks_per_cu", "ms")}
+                                     for c in tuned]},
             "over_budget": count - done, "tree_nodes": nodes, "seconds": dt, "kernel_ms": kms,
             "boxes_per_s": nodes / dt, "solves_per_s": count / dt,
             "plain": {"systems": plain_sample, "tree_nodes": pn, "seconds": pdt, "boxes_per_s": pn / pdt,

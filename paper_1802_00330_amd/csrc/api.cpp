@@ -304,9 +304,15 @@ int ensure_pinned(ibb_ctx* ctx, size_t need) {
 int resident_per_cu(ibb_ctx* ctx, const void* fn, int threads, size_t lds) {
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) return 0;
-  const size_t granule = 2048;
+  // The runtime's figure can exceed what becomes resident on a 160 KiB CU:
+  // workgroups needing 3 x 54,272 and 5 x 32,256 bytes (512-byte granules)
+  // were not all resident at once (a level's grid barrier waited in vain),
+  // while 5 x 31,744 = 158,720 bytes were.  Persistent launches therefore
+  // count 512-byte granules against the CU's LDS less 5 KiB.
+  const size_t granule = 512, reserve = 5120;
   const size_t rounded = (lds + granule - 1) / granule * granule;
-  if (rounded > 0 && ctx->lds_per_cu > 0) per_cu = std::min<int>(per_cu, (int)(ctx->lds_per_cu / rounded));
+  if (rounded > 0 && ctx->lds_per_cu > reserve)
+    per_cu = std::min<int>(per_cu, (int)((ctx->lds_per_cu - reserve) / rounded));
   return per_cu;
 }
 
