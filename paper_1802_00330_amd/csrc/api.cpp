@@ -821,6 +821,18 @@ int batch_finish(const BatchHost& h, char* w, const BatchLayout& L, long long oc
   return IBB_OK;
 }
 
+// First frontier capacity of a batch.  A level of a member holds at most half
+// of the member's node budget and the members' widest levels do not all
+// coincide, so a quarter of the summed budgets (each counted up to 2^20),
+// within [4 M, 64 M] boxes, or what an earlier batch on the context needed.
+long long batch_first_fcap(const ibb_ctx* ctx, int32_t B, const ibb_params* params, const int32_t* status) {
+  double sum = 0.0;
+  for (int b = 0; b < B; ++b)
+    if (status[b] == IBB_OK) sum += (double)std::min<int64_t>(params[b].max_boxes, 1LL << 20);
+  const long long f = std::min<long long>(1LL << 26, std::max<long long>(1LL << 22, (long long)(sum / 4.0)));
+  return std::max(f, ctx->batch_fcap);
+}
+
 bool batch_args_ok(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const double* lo, const double* hi,
                    const ibb_params* params) {
   return ctx && B >= 1 && systems && lo && hi && params;
@@ -850,10 +862,8 @@ int solve_batch_with(ibb_ctx* ctx, const ibb_batch_config* cfg, int32_t B, const
     for (int b = 0; b <= B; ++b) out_off[b] = 0;
     return IBB_OK;
   }
-  // capacities sized for the batch up front (an overflow re-runs the whole
-  // batch): large batches start at 16 M boxes per level, and a capacity a
-  // previous batch needed is reused
-  long long fcap = std::max<long long>({1LL << 22, B >= 1024 ? 1LL << 24 : 0LL, ctx->batch_fcap});
+  // capacities sized for the batch up front (an overflow re-runs the whole batch)
+  long long fcap = batch_first_fcap(ctx, B, params, status);
   long long ocap = std::max<long long>(1LL << 15, 16LL * B);
   hipStream_t s = ctx->stream;
   for (int attempt = 0; attempt < 10; ++attempt) {
@@ -1089,7 +1099,7 @@ extern "C" int ibb_batch_plan_create(ibb_ctx* ctx, int32_t B, const ibb_system* 
     p->stream = nullptr;
     st = IBB_ERR_DEVICE;
   }
-  p->fcap = std::max<long long>({1LL << 22, B >= 1024 ? 1LL << 24 : 0LL, ctx->batch_fcap});
+  p->fcap = batch_first_fcap(ctx, B, params, p->status0.data());
   p->ocap = std::max<long long>(1LL << 15, 16LL * B);
   if (!st && p->h.any) st = plan_build(p);
   if (st) {
