@@ -198,6 +198,9 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=64)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="arrival window of the served leg (0 = skip)")
+    ap.add_argument("--serve-light-rate", type=float, default=100.0,
+                    help="a second served run at an arrival rate the device keeps up with (0 = skip)")
+    ap.add_argument("--serve-light-seconds", type=float, default=2.0)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB copied by a plain device copy before the solves (counter calibration)")
     args = ap.parse_args()
@@ -330,6 +333,10 @@ def main():
     if args.serve_seconds > 0:
         out["served"] = served_leg(ctx, P, W, args.serve_rate, args.serve_seconds, log)
         log(f"[bench] served: {out['served']}")
+        if args.serve_light_rate > 0:
+            out["served_within_capacity"] = served_leg(ctx, P, W, args.serve_light_rate, args.serve_light_seconds,
+                                                       log)
+            log(f"[bench] served within capacity: {out['served_within_capacity']}")
     if args.cpu_sample > 0:
         log(f"[bench] timing the oracle on {args.cpu_sample} nodes")
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_sample)
