@@ -433,6 +433,7 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
   uint32_t sysid = 0;
   double p_tol = a.tol, p_ratio = a.ratio, p_hsw = a.hs_max_width;
   int p_split = a.split_mode, p_maxrc = a.max_rc;
+  unsigned long long room = 0;  // batches: nodes the system may add at the next level
   if (MULTI) {
     if (valid) sysid = a.sys[cur][idx];
     T = global_table(a.blobs + a.blob_off[sysid]);
@@ -449,9 +450,12 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
       if (total > (unsigned long long)sp.max_boxes) {
         if (r == 0) atomicCAS(&a.status_sys[sysid], 0, -2);
         valid = false;
-      } else if (r == 0) {
-        a.cum_sys[(size_t)(level & 1) * a.B + sysid] = total;
-        a.count_sys[(size_t)((level + 2) % 3) * a.B + sysid] = 0ull;
+      } else {
+        room = (unsigned long long)sp.max_boxes - total;
+        if (r == 0) {
+          a.cum_sys[(size_t)(level & 1) * a.B + sysid] = total;
+          a.count_sys[(size_t)((level + 2) % 3) * a.B + sysid] = 0ull;
+        }
       }
     }
   }
@@ -806,6 +810,23 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
     }
   }
 
+  // Batches: once the next level alone takes a system over its budget, the
+  // system fails when that level is loaded whatever its other boxes do, so
+  // the children need not be stored (a budget failure would otherwise fill
+  // the frontier with boxes that are only read to be dropped).  They are
+  // still counted, which keeps that check, and every counter, as it was.
+  // The count read here lacks this group's children and perhaps others', so
+  // the test never fires for a system that stays within its budget.
+  bool store = true;
+  if (MULTI && !QUEUE && n_push > 0) {
+    const unsigned long long seen = __hip_atomic_load(&a.count_sys[(size_t)((level + 1) % 3) * a.B + sysid],
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (seen + (unsigned long long)n_push > room) {
+      store = false;
+      if (r == 0) atomicCAS(&a.status_sys[sysid], 0, -2);
+    }
+  }
+
   // ---- counters, once per group
   const bool leader = (r == 0) && valid;
   if (MULTI) {
@@ -821,8 +842,8 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
     sys_add(st + kEmitUnd, o8, (emit && tag == 0) ? 1u : 0u, leader);
     sys_add(a.count_sys + (size_t)((level + 1) % 3) * a.B, sysid, (unsigned)n_push, leader);
     if (a.pending_sys) {
-      // boxes still to step: + children pushed - this box (two's complement)
-      sys_add(a.pending_sys, sysid, (unsigned)(n_push - 1), leader);
+      // boxes still to step: + children stored - this box (two's complement)
+      sys_add(a.pending_sys, sysid, (unsigned)((store ? n_push : 0) - 1), leader);
       const bool dropped = (idx < cnt) && !valid && r == 0;  // over the budget
       sys_add(a.pending_sys, sysid, 0xFFFFFFFFu, dropped);
     }
@@ -839,7 +860,7 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
   sc.add(kEmitUnd, (unsigned long long)(__popcll(__ballot(leader && emit && tag == 0))));
 
   // ---- compaction: one atomic per wave for the pushes, one for the emits
-  const unsigned my_push = (r == 0) ? (unsigned)n_push : 0u;
+  const unsigned my_push = (r == 0 && store) ? (unsigned)n_push : 0u;
   const unsigned my_emit = (r == 0 && emit) ? 1u : 0u;
   const unsigned incl_p = wave_inclusive_sum(my_push);
   const unsigned incl_e = wave_inclusive_sum(my_emit);
@@ -897,7 +918,7 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
   // writes into the reserved ring items once their slots are free
   const unsigned long long o = pbase + gp;
   int pushed = 0;
-  if (n_push) {
+  if (n_push && store) {
     const iv x = row_ok ? S.Xn[g][r] : iv{0.0, 0.0};
     const bool mine = (split_mask >> r) & 1u;
     const int q = __popc(split_mask & ((1u << r) - 1u));
