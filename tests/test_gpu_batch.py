@@ -171,6 +171,10 @@ def test_batch_set_config_rejects_invalid(gpu_ctx):
         P.ibb_batch_set_config(gpu_ctx, 1, 16, 16, 3)
         c = P.ibb_batch_get_config(gpu_ctx, 1)
         assert (c.lanes, c.tiles_per_claim, c.blocks_per_cu, c.tuned) == (16, 16, 3, 0)
+        with pytest.raises(RuntimeError, match="invalid"):
+            P.ibb_batch_tune(gpu_ctx, [W.circle_line()], sample=0)
+        with pytest.raises(RuntimeError, match="invalid"):
+            P.ibb_batch_get_config(gpu_ctx, 4)
     finally:
         _defaults(P, gpu_ctx)
     assert P.ibb_batch_get_config(gpu_ctx, 1).lanes == 4
