@@ -296,11 +296,10 @@ int ensure_pinned(ibb_ctx* ctx, size_t need) {
   return IBB_OK;
 }
 
-// Launch geometry of a persistent kernel: waves per block, LDS, grid.
 // Workgroups of a persistent launch that are resident on one CU at once.
 // The occupancy query alone over-promises near the LDS limit (measured on
 // gfx950: three workgroups of 53,952 B were reported to fit the 160 KiB of a
-// CU, two were resident); LDS is therefore also counted in 2 KiB granules.
+// CU, two were resident); LDS is therefore also counted in granules.
 int resident_per_cu(ibb_ctx* ctx, const void* fn, int threads, size_t lds) {
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) return 0;

@@ -816,15 +816,22 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
   // the frontier with boxes that are only read to be dropped).  They are
   // still counted, which keeps that check, and every counter, as it was.
   // The count read here lacks this group's children and perhaps others', so
-  // the test never fires for a system that stays within its budget.
+  // the test never fires for a system that stays within its budget.  Other
+  // waves update the count meanwhile, so it is read once per group (by its
+  // first lane) and the decision is broadcast: every lane of a group must
+  // agree with the reservation its first lane makes below.
   bool store = true;
-  if (MULTI && !QUEUE && n_push > 0) {
-    const unsigned long long seen = __hip_atomic_load(&a.count_sys[(size_t)((level + 1) % 3) * a.B + sysid],
-                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (seen + (unsigned long long)n_push > room) {
-      store = false;
-      if (r == 0) atomicCAS(&a.status_sys[sysid], 0, -2);
+  if (MULTI && !QUEUE) {
+    int drop = 0;
+    if (r == 0 && n_push > 0) {
+      const unsigned long long seen = __hip_atomic_load(&a.count_sys[(size_t)((level + 1) % 3) * a.B + sysid],
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (seen + (unsigned long long)n_push > room) {
+        drop = 1;
+        atomicCAS(&a.status_sys[sysid], 0, -2);
+      }
     }
+    store = __shfl(drop, g * G, 64) == 0;
   }
 
   // ---- counters, once per group

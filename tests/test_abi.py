@@ -54,3 +54,61 @@ def test_build_rejects_scratch_in_search_kernels():
     bad = ok.replace("ScratchSize [bytes/lane]: 0", "ScratchSize [bytes/lane]: 196")
     with pytest.raises(RuntimeError):
         check_no_scratch(bad)
+
+
+def test_build_rejects_scratch_in_queue_kernel():
+    """The work-queue search kernel is held to the same no-scratch rule."""
+    from paper_1802_00330_amd.build import check_no_scratch
+    ok = ("k.hip:1:1: remark: Function Name: _ZN3ibb12queue_kernelILi16EEEvNS_9SolveArgsE\n"
+          "k.hip:1:1: remark:     ScratchSize [bytes/lane]: 0\n")
+    check_no_scratch(ok)
+    with pytest.raises(RuntimeError):
+        check_no_scratch(ok.replace("ScratchSize [bytes/lane]: 0", "ScratchSize [bytes/lane]: 8"))
+
+
+_ASM = """\
+_ZN3ibb12solve_kernelILi8ELb0EEEvNS_9SolveArgsE:
+\t;;#ASMSTART
+\ts_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2
+\t;;#ASMEND
+\t;;#ASMSTART
+\tv_add_f64 v[0:1], v[2:3], v[4:5]
+\t;;#ASMEND
+\tv_cvt_f64_f32_e32 v[6:7], v8
+\tv_rcp_f64_e32 v[6:7], v[6:7]
+\tv_max_f64 v[0:1], v[0:1], v[2:3]
+\ts_endpgm
+_ZN3ibb11sort_kernelEPKd:
+\tv_add_f64 v[0:1], v[2:3], v[4:5]
+\ts_endpgm
+"""
+
+
+def test_isa_check_accepts_directed_kernels():
+    """One MODE write at entry, FP64 arithmetic only in the one-instruction
+    statements; kernels without a rounding-mode change are not restricted."""
+    from paper_1802_00330_amd.build import check_isa
+    check_isa(_ASM)
+
+
+@pytest.mark.parametrize("planted", [
+    "\tv_add_f64 v[0:1], v[2:3], v[4:5]\n",          # compiler FP64 add in round-down code
+    "\tv_fma_f64 v[0:1], v[2:3], v[4:5], v[6:7]\n",  # compiler FP64 fma
+    "\ts_round_mode 0x0\n",                         # a second MODE write
+    "\ts_setreg_imm32_b32 hwreg(HW_REG_MODE, 0, 4), 0\n",
+    "\tv_pk_mul_f32 v[0:1], v[2:3], v[4:5]\n",       # packed FP32
+])
+def test_isa_check_rejects(planted):
+    from paper_1802_00330_amd.build import check_isa
+    at = _ASM.index("\tv_cvt_f64_f32_e32")
+    with pytest.raises(RuntimeError):
+        check_isa(_ASM[:at] + planted + _ASM[at:])
+
+
+def test_built_library_passed_the_isa_check():
+    """The device assembly kept by the last build satisfies check_isa."""
+    from paper_1802_00330_amd import build
+    s = os.path.join(build.HERE, "_build", "kernels-hip-amdgcn-amd-amdhsa-gfx950.s")
+    if not os.path.exists(s):
+        pytest.skip("library not built in this tree")
+    build.check_isa(open(s).read())
