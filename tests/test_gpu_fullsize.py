@@ -13,12 +13,12 @@ pytestmark = pytest.mark.gpu
 
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
-CASES = {
-    "dense6_s0": lambda: W.dense_planted(0),
-    "dense6_s1": lambda: W.dense_planted(1),
-    "banded12_s0": lambda: W.banded(0),
-    "banded12_s1": lambda: W.banded(1),
-}
+# the dense n=6 and banded n=12 workloads, seeds 0..4 (up to 16.8 million
+# tree nodes per solve)
+CASES = {}
+for _k in range(5):
+    CASES[f"dense6_s{_k}"] = (lambda k: lambda: W.dense_planted(k))(_k)
+    CASES[f"banded12_s{_k}"] = (lambda k: lambda: W.banded(k))(_k)
 
 
 def _load(name):

@@ -29,6 +29,25 @@ def test_circle_line_split_all(gpu_ctx, oracle_lib):
     assert_same(gpu, ref, "circle_line ALL")
 
 
+# the paper's all-coordinate split (Alg. 2: 2^n children) with the
+# contraction on, at n = 3 and 4 (8 and 16 children per split)
+SPLIT_ALL_CASES = {
+    "product3": lambda: W.product_linear([4, 3], n=3),
+    "product4": lambda: W.product_linear([4, 4], n=4),
+    "dense4": lambda: W.dense_planted(0, n=4, n_terms=6, max_deg=2),
+    "dense3_cubic": lambda: W.dense_planted(1, n=3, n_terms=6, max_deg=3),
+    "banded4": lambda: W.banded(0, n=4, tol=1e-8),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SPLIT_ALL_CASES))
+def test_split_all_with_contraction(gpu_ctx, oracle_lib, name):
+    s = SPLIT_ALL_CASES[name]()
+    gpu, ref = _both(gpu_ctx, oracle_lib, s, split_mode=1)
+    assert ref.stats["excluded_hs"] + ref.stats["recontracted"] > 0  # the contraction acted
+    assert_same(gpu, ref, f"{name} ALL")
+
+
 def test_host_pointer_entry_point(gpu_ctx, oracle_lib):
     import paper_1802_00330_amd as P
     s = W.circle_line()

@@ -1,7 +1,6 @@
 """The stored oracle results are reproducible: re-running the oracle's single
 contraction step on the stored proof-chain boxes gives the stored boxes (a
 check that the oracle computes the same on any host)."""
-import glob
 import json
 import os
 
@@ -14,12 +13,15 @@ MAKERS = {"dense6_s0": lambda: W.dense_planted(0), "dense6_s1": lambda: W.dense_
           "banded12_s0": lambda: W.banded(0), "banded12_s1": lambda: W.banded(1)}
 
 
-@pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(os.path.dirname(__file__), "golden",
-                                                                "expected_*.json"))))
+# the stored results that carry proof chains (make_expected.py stores them for
+# the cases of MAKERS only)
+PATHS = [os.path.join(os.path.dirname(__file__), "golden", f"expected_{k}.json") for k in sorted(MAKERS)]
+
+
+@pytest.mark.parametrize("path", PATHS)
 def test_stored_chains_reproduce(oracle_lib, path):
     g = json.load(open(path))
-    if "chains" not in g:
-        pytest.skip("no chains stored")
+    assert "chains" in g, path
     s = MAKERS[g["case"]]()
     for k, c in enumerate(g["chains"]):
         lo, hi, elo, ehi = (np.array([float.fromhex(v) for v in a]) for a in c)
