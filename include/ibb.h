@@ -44,6 +44,7 @@ extern "C" {
 #define IBB_ERR_DEVICE (-6)          /* a HIP runtime call failed                      */
 #define IBB_ERR_UNSUPPORTED (-7)     /* valid request outside this build's limits      */
 #define IBB_ERR_TIMEOUT (-8)         /* a device-side wait exceeded its time limit     */
+#define IBB_ERR_WORKSPACE_LIMIT (-9) /* ibb_solve_noalloc: workspace above its maximum */
 
 /* ---- limits ---- */
 #define IBB_MAX_N 16      /* equations = variables                        */
@@ -281,6 +282,29 @@ int ibb_solve_async(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const
                     const ibb_params* params, void* d_ws, size_t ws_bytes, int64_t frontier_cap,
                     int64_t out_cap, double* d_out_lo, double* d_out_hi, uint8_t* d_out_tag,
                     int64_t* d_info, void* stream);
+
+/* ---- allocation-free solve ----
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * solve as ibb_solve_async (same arguments, outputs, d_info and results),
+ * except that the workspace is not passed in: it is the library's own array
+ * of IBB_NOALLOC_WORKSPACE_BYTES bytes on the context's device, a file-scope
+ * device array that each GPU the library runs on holds until the process
+ * ends.  The call allocates no device memory and no pinned host memory (the
+ * context reserves its pinned staging buffer for the largest system when it
+ * is created); the system is compiled on the host as in every entry point.
+ * Returns IBB_ERR_WORKSPACE_LIMIT, with nothing enqueued, when
+ * ibb_workspace_size(n, frontier_cap, out_cap) exceeds the array (for
+ * example n <= 8 with out_cap 4096 allows a frontier of about 168,000 boxes,
+ * n <= 16 about 85,000).  Every call on one device shares that device's
+ * array, whichever context makes it: calls whose device work overlaps race
+ * and their results are undefined, so order them (e.g. enqueue them on one
+ * stream).  The array keeps the last call's contents; each call initialises
+ * every part of it that the solve reads. */
+#define IBB_NOALLOC_WORKSPACE_BYTES (64ull << 20)
+int ibb_solve_noalloc(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const double* hi,
+                      const ibb_params* params, int64_t frontier_cap, int64_t out_cap, double* d_out_lo,
+                      double* d_out_hi, uint8_t* d_out_tag, int64_t* d_info, void* stream);
 
 /* Per-level frontier sizes of the most recent ibb_solve on this context
  * (level 0 = the initial box): copies min(count, cap) values, returns the

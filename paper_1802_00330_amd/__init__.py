@@ -24,6 +24,8 @@ OK = 0
 SCHEDULE_QUEUE, SCHEDULE_LEVELS, SCHEDULE_AUTO = 0, 1, 2
 ERR_INVALID_ARG, ERR_BUDGET, ERR_OUTPUT_CAPACITY, ERR_QUEUE_OVERFLOW = -1, -2, -3, -4
 ERR_NO_MEMORY, ERR_DEVICE, ERR_UNSUPPORTED, ERR_TIMEOUT = -5, -6, -7, -8
+ERR_WORKSPACE_LIMIT = -9
+NOALLOC_WORKSPACE_BYTES = 64 << 20
 SPLIT_WIDEST, SPLIT_ALL = 0, 1
 UNDECIDED, UNIQUE = 0, 1
 MAX_N = 16
@@ -36,7 +38,8 @@ EXPORTS = ("ibb_ctx_create", "ibb_ctx_destroy", "ibb_strerror", "ibb_params_defa
            "ibb_selftest_ops", "ibb_debug_step", "ibb_solve_batch", "ibb_server_config_default",
            "ibb_server_create", "ibb_server_destroy", "ibb_server_submit", "ibb_server_step", "ibb_server_poll",
            "ibb_server_cancel", "ibb_server_pending", "ibb_round", "ibb_batch_plan_create", "ibb_batch_plan_run",
-           "ibb_batch_plan_destroy", "ibb_batch_get_config", "ibb_batch_set_config", "ibb_batch_tune")
+           "ibb_batch_plan_destroy", "ibb_batch_get_config", "ibb_batch_set_config", "ibb_batch_tune",
+           "ibb_solve_noalloc")
 
 
 class IbbSystem(C.Structure):
@@ -95,6 +98,8 @@ def load_library(path: str = LIB_PATH):
     L.ibb_solve_async.restype = C.c_int
     L.ibb_solve_async.argtypes = [p, C.POINTER(IbbSystem), p, p, C.POINTER(IbbParams), p, C.c_size_t, i64, i64,
                                   p, p, p, p, p]
+    L.ibb_solve_noalloc.restype = C.c_int
+    L.ibb_solve_noalloc.argtypes = [p, C.POINTER(IbbSystem), p, p, C.POINTER(IbbParams), i64, i64, p, p, p, p, p]
     L.ibb_last_level_sizes.restype, L.ibb_last_level_sizes.argtypes = i64, [p, p, i64]
     L.ibb_selftest_ops.restype, L.ibb_selftest_ops.argtypes = C.c_int, [p, i32, i64, p, p, p]
     L.ibb_last_kernel_ms.restype, L.ibb_last_kernel_ms.argtypes = C.c_double, [p]
@@ -257,6 +262,27 @@ def ibb_solve_async(ctx: Context, s, params: IbbParams, ws, frontier_cap: int, o
                                           int(out_cap), C.c_void_p(addr(out_lo)), C.c_void_p(addr(out_hi)),
                                           C.c_void_p(addr(out_tag)), C.c_void_p(addr(info)),
                                           C.c_void_p(sh))
+
+
+def ibb_solve_noalloc(ctx: Context, s, params: IbbParams, frontier_cap: int, out_cap: int,
+                      out_lo, out_hi, out_tag, info, stream=None, lo=None, hi=None) -> int:
+    """ibb_solve_async on the library's own per-device workspace array (no
+    device allocation): out_*/info are torch CUDA tensors or device addresses."""
+    import torch
+
+    def addr(t):
+        return t.data_ptr() if isinstance(t, torch.Tensor) else int(t)
+
+    ref = _SysRef(s)
+    lo = np.ascontiguousarray(s.lo if lo is None else lo, dtype=np.float64)
+    hi = np.ascontiguousarray(s.hi if hi is None else hi, dtype=np.float64)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    return load_library().ibb_solve_noalloc(ctx.handle, C.byref(ref.c), _ptr(lo), _ptr(hi), C.byref(params),
+                                            int(frontier_cap), int(out_cap), C.c_void_p(addr(out_lo)),
+                                            C.c_void_p(addr(out_hi)), C.c_void_p(addr(out_tag)),
+                                            C.c_void_p(addr(info)), C.c_void_p(sh))
 
 
 def solve(ctx: Context, s, tol: Optional[float] = None, frontier_cap: int = 1 << 20, out_cap: int = 1 << 12,

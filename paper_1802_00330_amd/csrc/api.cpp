@@ -43,6 +43,7 @@ hipError_t launch_queue_init(hipStream_t s, unsigned long long* seq, long long c
 hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, long long count, unsigned long long v);
 hipError_t launch_selftest(hipStream_t s, int op, long long count, const double* x, const double* y,
                            double* out);
+hipError_t noalloc_scratch(int device, void** ptr);
 }  // namespace ibb
 
 using namespace ibb;
@@ -249,6 +250,7 @@ struct ibb_ctx {
   long long* info = nullptr;
   char* pinned = nullptr;  // host staging of the inputs
   size_t pinned_bytes = 0;
+  void* noalloc_ws = nullptr;  // device address of the allocation-free workspace
   std::vector<long long> last_levels;
   void* bws = nullptr;  // batch workspace
   size_t bws_bytes = 0;
@@ -1163,6 +1165,7 @@ const char* ibb_strerror(int s) {
     case IBB_ERR_DEVICE: return "HIP runtime error";
     case IBB_ERR_UNSUPPORTED: return "unsupported by this build";
     case IBB_ERR_TIMEOUT: return "device wait timed out";
+    case IBB_ERR_WORKSPACE_LIMIT: return "workspace larger than the allocation-free maximum";
     default: return "unknown status";
   }
 }
@@ -1206,6 +1209,16 @@ int ibb_ctx_create(int device, ibb_ctx** out) {
       hipMalloc(reinterpret_cast<void**>(&c->info), sizeof(long long) * kInfoLen) != hipSuccess) {
     ibb_ctx_destroy(c);
     return IBB_ERR_DEVICE;
+  }
+  // the allocation-free solve: the workspace array's address on this device,
+  // and a pinned staging buffer that holds the largest system's inputs
+  if (noalloc_scratch(device, &c->noalloc_ws) != hipSuccess) {
+    ibb_ctx_destroy(c);
+    return IBB_ERR_DEVICE;
+  }
+  if (ensure_pinned(c, 8 * max_blob_words(IBB_MAX_N) + 2 * sizeof(double) * kMaxN) != IBB_OK) {
+    ibb_ctx_destroy(c);
+    return IBB_ERR_NO_MEMORY;
   }
   *out = c;
   return IBB_OK;
@@ -1253,6 +1266,31 @@ int ibb_solve_async(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const
   const WsLayout L = ws_layout(c.n, max_blob_words(c.n), frontier_cap, out_cap);
   return enqueue_solve(ctx, c, lo, hi, params, static_cast<char*>(d_ws), L, frontier_cap, out_cap, d_out_lo,
                        d_out_hi, d_out_tag, reinterpret_cast<long long*>(d_info),
+                       static_cast<hipStream_t>(stream));
+}
+
+// The solve of ibb_solve_async with the device's own workspace array: no
+// device or pinned allocation (the pinned staging buffer was sized for the
+// largest system when the context was created, so enqueue_solve reuses it).
+int ibb_solve_noalloc(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const double* hi,
+                      const ibb_params* params, int64_t frontier_cap, int64_t out_cap, double* d_out_lo,
+                      double* d_out_hi, uint8_t* d_out_tag, int64_t* d_info, void* stream) {
+  if (!ctx || !ctx->noalloc_ws || !d_info || frontier_cap < 1 || out_cap < 0) return IBB_ERR_INVALID_ARG;
+  if (out_cap > 0 && (!d_out_lo || !d_out_hi || !d_out_tag)) return IBB_ERR_INVALID_ARG;
+  int st = validate(sys, lo, hi, params);
+  if (st) return st;
+  if (ibb_workspace_size(sys->n, frontier_cap, out_cap) > (size_t)IBB_NOALLOC_WORKSPACE_BYTES)
+    return IBB_ERR_WORKSPACE_LIMIT;
+  if (hipSetDevice(ctx->device) != hipSuccess) return IBB_ERR_DEVICE;
+  Compiled c;
+  try {
+    compile(sys, c);
+  } catch (...) {
+    return IBB_ERR_NO_MEMORY;
+  }
+  const WsLayout L = ws_layout(c.n, max_blob_words(c.n), frontier_cap, out_cap);
+  return enqueue_solve(ctx, c, lo, hi, params, static_cast<char*>(ctx->noalloc_ws), L, frontier_cap, out_cap,
+                       d_out_lo, d_out_hi, d_out_tag, reinterpret_cast<long long*>(d_info),
                        static_cast<hipStream_t>(stream));
 }
 

@@ -13,7 +13,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
+#include "../../include/ibb.h"
 #include "interval.hpp"
 #include "layout.hpp"
 
@@ -1613,6 +1615,37 @@ hipError_t launch_slot_sort(hipStream_t s, const double* box, const uint32_t* ta
   hipLaunchKernelGGL(slot_sort_kernel, dim3((cap + 255) / 256), dim3(256), 0, s, box, tag, slot_count, slot, cap,
                      n, out_lo, out_hi, out_tag);
   return hipGetLastError();
+}
+
+}  // namespace ibb
+
+// ---------------------------------------------------------------------------
+// Workspace of the allocation-free solve (ibb_solve_noalloc): one array per
+// device, held from the first use of the library on that device until the
+// process ends.  Host code never uses the array's name as an address (on the
+// host it names a stand-in, not device memory); it uses the address that
+// hipGetSymbolAddress returns on each device, looked up once per device.
+// ---------------------------------------------------------------------------
+namespace ibb {
+
+static __device__ __align__(256) unsigned char scratch[IBB_NOALLOC_WORKSPACE_BYTES];
+
+// The device address of `scratch` on `device`, which must be the current
+// device; hipSuccess or the lookup's error.
+hipError_t noalloc_scratch(int device, void** ptr) {
+  constexpr int kDevices = 64;
+  static std::mutex mu;
+  static void* addr[kDevices] = {};
+  if (device < 0 || device >= kDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
 }
 
 }  // namespace ibb
