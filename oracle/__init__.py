@@ -26,6 +26,8 @@ STATS_FIELDS = ("processed", "excluded_eval", "excluded_hs", "hs_skipped", "reco
 
 OK, ERR_INVALID_ARG, ERR_BUDGET, ERR_OUTPUT_CAPACITY = 0, -1, -2, -3
 SPLIT_WIDEST, SPLIT_ALL = 0, 1
+CONTRACT_HS, CONTRACT_KRAWCZYK = 0, 1
+INCLUDE_NATURAL, INCLUDE_MEAN_VALUE = 0, 1
 HS_EMPTY, HS_SKIPPED, HS_DONE = 0, 1, 2
 
 
@@ -56,17 +58,19 @@ def lib():
         L.oracle_eval_F.restype, L.oracle_eval_F.argtypes = None, [C.c_int, p, p, p, p, p, p, p]
         L.oracle_eval_J.restype, L.oracle_eval_J.argtypes = None, [C.c_int, p, p, p, p, p, p, p]
         L.oracle_fp32_inverse.restype, L.oracle_fp32_inverse.argtypes = C.c_int, [C.c_int, p, p]
-        L.oracle_hs.restype, L.oracle_hs.argtypes = C.c_int, [C.c_int, p, p, p, p, p, p, p, p]
+        L.oracle_hs.restype, L.oracle_hs.argtypes = C.c_int, [C.c_int, p, p, p, p, p, p, p, p, C.c_int]
+        L.oracle_exclusion_keep.restype = None
+        L.oracle_exclusion_keep.argtypes = [C.c_int, p, p, p, i64, p, p, p]
         L.oracle_set_chain.restype, L.oracle_set_chain.argtypes = None, [p, i64]
         L.oracle_chain_len.restype, L.oracle_chain_len.argtypes = i64, []
         L.oracle_hs_trace.restype = C.c_int
-        L.oracle_hs_trace.argtypes = [C.c_int, p, p, p, p, p, p]
+        L.oracle_hs_trace.argtypes = [C.c_int, p, p, p, p, p, p, C.c_int]
         L.oracle_solve.restype = C.c_int
         L.oracle_solve.argtypes = [C.c_int, p, p, p, p, p, d, i64, i32, i32, d, d,
-                                   p, p, p, i64, p, p, C.c_int, C.c_uint64]
+                                   p, p, p, i64, p, p, C.c_int, C.c_uint64, i32, i32]
         L.oracle_round.restype = C.c_int
         L.oracle_round.argtypes = [C.c_int, p, p, p, i64, p, p, p, d, i32, i32, d, d,
-                                   p, p, p, i64, p, p, p, p, i64, p, p]
+                                   p, p, p, i64, p, p, p, p, i64, p, p, i32, i32]
         _lib = L
     return _lib
 
@@ -128,6 +132,16 @@ def eval_J(s, lo, hi):
     return olo, ohi
 
 
+def exclusion_keep(s, lo, hi):
+    """The exclusion test on many boxes (rows of lo/hi): True where the box is kept."""
+    to, ex, co = _sys_arrays(s)
+    lo = np.ascontiguousarray(lo, dtype=np.float64).reshape(-1, s.n)
+    hi = np.ascontiguousarray(hi, dtype=np.float64).reshape(-1, s.n)
+    keep = np.zeros(lo.shape[0], dtype=np.uint8)
+    lib().oracle_exclusion_keep(s.n, _ptr(to), _ptr(ex), _ptr(co), int(lo.shape[0]), _ptr(lo), _ptr(hi), _ptr(keep))
+    return keep.astype(bool)
+
+
 def fp32_inverse(M):
     M = np.ascontiguousarray(M, dtype=np.float32)
     n = M.shape[0]
@@ -136,25 +150,26 @@ def fp32_inverse(M):
     return (Y if st == 0 else None)
 
 
-def hs(s, lo, hi):
-    """One Hansen-Sengupta step: (status, lo', hi', unique)."""
+def hs(s, lo, hi, contractor: int = CONTRACT_HS):
+    """One contraction step (Hansen-Sengupta, or Krawczyk with
+    contractor=CONTRACT_KRAWCZYK): (status, lo', hi', unique)."""
     to, ex, co = _sys_arrays(s)
     lo = np.ascontiguousarray(lo, dtype=np.float64)
     hi = np.ascontiguousarray(hi, dtype=np.float64)
     olo, ohi = lo.copy(), hi.copy()
     u = C.c_int(0)
     st = lib().oracle_hs(s.n, _ptr(to), _ptr(ex), _ptr(co), _ptr(lo), _ptr(hi), _ptr(olo), _ptr(ohi),
-                         C.byref(u))
+                         C.byref(u), int(contractor))
     return st, olo, ohi, bool(u.value)
 
 
-def hs_trace(s, lo, hi):
+def hs_trace(s, lo, hi, contractor: int = CONTRACT_HS):
     """Intermediates of one contraction step (layout: see oracle_hs_trace)."""
     to, ex, co = _sys_arrays(s)
     lo = np.ascontiguousarray(lo, dtype=np.float64)
     hi = np.ascontiguousarray(hi, dtype=np.float64)
     tr = np.zeros(6 * s.n * s.n + 8 * s.n + 4)
-    st = lib().oracle_hs_trace(s.n, _ptr(to), _ptr(ex), _ptr(co), _ptr(lo), _ptr(hi), _ptr(tr))
+    st = lib().oracle_hs_trace(s.n, _ptr(to), _ptr(ex), _ptr(co), _ptr(lo), _ptr(hi), _ptr(tr), int(contractor))
     return st, tr
 
 
@@ -183,7 +198,8 @@ class Result:
 
 def solve(s, tol: Optional[float] = None, max_boxes: int = 10_000_000, split_mode: int = SPLIT_WIDEST,
           max_recontract: int = 16, recontract_ratio: float = 0.5, hs_max_width: float = float("inf"),
-          cap: int = 1 << 16, order: int = 0, seed: int = 0, lo=None, hi=None) -> Result:
+          cap: int = 1 << 16, order: int = 0, seed: int = 0, lo=None, hi=None,
+          contractor: int = CONTRACT_HS, inclusion: int = INCLUDE_NATURAL) -> Result:
     to, ex, co = _sys_arrays(s)
     lo = np.ascontiguousarray(s.lo if lo is None else lo, dtype=np.float64)
     hi = np.ascontiguousarray(s.hi if hi is None else hi, dtype=np.float64)
@@ -197,7 +213,8 @@ def solve(s, tol: Optional[float] = None, max_boxes: int = 10_000_000, split_mod
         st = lib().oracle_solve(s.n, _ptr(to), _ptr(ex), _ptr(co), _ptr(lo), _ptr(hi), float(tol),
                                 int(max_boxes), int(split_mode), int(max_recontract),
                                 float(recontract_ratio), float(hs_max_width), _ptr(olo), _ptr(ohi),
-                                _ptr(otag), int(cap), C.byref(nout), _ptr(stats), int(order), int(seed))
+                                _ptr(otag), int(cap), C.byref(nout), _ptr(stats), int(order), int(seed),
+                                int(contractor), int(inclusion))
         if st == ERR_OUTPUT_CAPACITY:
             cap = int(nout.value)
             continue
@@ -220,7 +237,8 @@ class Round:
 
 def round_step(s, lo, hi, rec=None, tol: Optional[float] = None, split_mode: int = SPLIT_WIDEST,
                max_recontract: int = 16, recontract_ratio: float = 0.5,
-               hs_max_width: float = float("inf")) -> Round:
+               hs_max_width: float = float("inf"), contractor: int = CONTRACT_HS,
+               inclusion: int = INCLUDE_NATURAL) -> Round:
     """One round of the search on the boxes lo[b], hi[b] (see oracle_round)."""
     to, ex, co = _sys_arrays(s)
     lo = np.ascontiguousarray(np.asarray(lo, dtype=np.float64).reshape(-1, s.n))
@@ -239,7 +257,8 @@ def round_step(s, lo, hi, rec=None, tol: Optional[float] = None, split_mode: int
         st = lib().oracle_round(s.n, _ptr(to), _ptr(ex), _ptr(co), int(m), _ptr(lo), _ptr(hi), _ptr(rec),
                                 float(tol), int(split_mode), int(max_recontract), float(recontract_ratio),
                                 float(hs_max_width), _ptr(clo), _ptr(chi), _ptr(crec), int(ccap), C.byref(nc),
-                                _ptr(elo), _ptr(ehi), _ptr(etag), int(ecap), C.byref(ne), _ptr(stats))
+                                _ptr(elo), _ptr(ehi), _ptr(etag), int(ecap), C.byref(ne), _ptr(stats),
+                                int(contractor), int(inclusion))
         if st == ERR_OUTPUT_CAPACITY:
             ccap, ecap = max(ccap, int(nc.value)), max(ecap, int(ne.value))
             continue

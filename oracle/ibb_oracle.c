@@ -434,7 +434,10 @@ static int tr_flags(int n) { return 6 * n * n + 8 * n; }
 /* Y (a point, exactly representable) times an interval. */
 static ival pmul(double y, ival x) { return i_mul(iv(y, y), x); }
 
-static int hs_step(const osys* s, const ival* X, ival* Xn, int* unique) {
+#define OR_CONTRACT_HS 0
+#define OR_CONTRACT_KRAWCZYK 1
+
+static int hs_step(const osys* s, const ival* X, ival* Xn, int* unique, int contractor) {
   const int n = s->n;
   double xc[OR_MAX_N];
   ival Xc[OR_MAX_N], Fc[OR_MAX_N], D[OR_MAX_N];
@@ -517,6 +520,45 @@ static int hs_step(const osys* s, const ival* X, ival* Xn, int* unique) {
   /* X - x, eq (19) */
   for (int k = 0; k < n; ++k) D[k] = i_sub(X[k], Xc[k]);
 
+  if (contractor == OR_CONTRACT_KRAWCZYK) {
+    /* Krawczyk operator, eq (15): K(X) = x - B f(x) + [I - B J(X)](X - x), with
+     * B f(x) = g and B J(X) = P as above; every component uses X (no update as
+     * the components are obtained).  The sum over j ascending starts from its
+     * first term; K_i = (x_i - g_i) + sum.  Eq (16): X' = X meets K(X); an
+     * empty meet means no root; K(X) inside the interior of X proves one. */
+    int uniq = 1;
+    for (int i = 0; i < n; ++i) {
+      ival sum = iv(0, 0);
+      for (int j = 0; j < n; ++j) {
+        ival m = (j == i) ? i_sub(iv(1.0, 1.0), P[i][j]) : iv(-P[i][j].hi, -P[i][j].lo);
+        ival t = i_mul(m, D[j]);
+        sum = j ? i_add(sum, t) : t;
+      }
+      ival K = i_add(i_sub(Xc[i], g[i]), sum);
+      if (g_trace) {
+        g_trace[tr_N(n) + 2 * i] = K.lo;
+        g_trace[tr_N(n) + 2 * i + 1] = K.hi;
+      }
+      double a = max2(K.lo, X[i].lo), b = min2(K.hi, X[i].hi);
+      if (a > b) {
+        if (g_trace) g_trace[tr_flags(n) + 1] = 1.0;
+        return HS_EMPTY;
+      }
+      uniq = uniq && X[i].lo < K.lo && K.hi < X[i].hi;
+      Xn[i] = iv(a, b);
+      if (g_trace) {
+        g_trace[tr_X(n) + 2 * i] = a;
+        g_trace[tr_X(n) + 2 * i + 1] = b;
+      }
+    }
+    *unique = uniq;
+    if (g_trace) {
+      g_trace[tr_flags(n) + 2] = uniq ? 1.0 : 0.0;
+      g_trace[tr_flags(n) + 3] = 1.0;
+    }
+    return HS_DONE;
+  }
+
   /* Gauss-Seidel sweep, eq (21)-(22):
    *   Y_i = x_i - (P_ii)^{-1} [ g_i + sum_{j<i} P_ij (X'_j - x_j) + sum_{j>i} P_ij (X_j - x_j) ]
    * The bracket is evaluated as written: the two sums are formed separately
@@ -588,10 +630,29 @@ static int hs_step(const osys* s, const ival* X, ival* Xn, int* unique) {
   return HS_DONE;
 }
 
+/* The exclusion test (Def. 2) on m boxes (row-major [m][n] bounds): keep[b] = 1
+ * when every F_i holds 0 over box b, else 0.  Used to count the boxes kept by
+ * the rounds of the paper's worked examples. */
+void oracle_exclusion_keep(int n, const int32_t* term_off, const uint8_t* expo, const double* coef, int64_t m,
+                           const double* lo, const double* hi, uint8_t* keep) {
+  KEEP_CALLER_MODE;
+  osys s = make_sys(n, term_off, expo, coef);
+  for (int64_t b = 0; b < m; ++b) {
+    ival X[OR_MAX_N];
+    for (int k = 0; k < n; ++k) X[k] = iv(lo[b * n + k], hi[b * n + k]);
+    int kept = 1;
+    for (int i = 0; i < n && kept; ++i) {
+      ival f = eval_f(&s, i, X);
+      if (f.lo > 0 || f.hi < 0) kept = 0;
+    }
+    keep[b] = (uint8_t)kept;
+  }
+}
+
 /* One contraction step with its intermediates written to `trace`
  * (6n^2 + 8n + 4 doubles, layout of tr_* above). */
 int oracle_hs_trace(int n, const int32_t* term_off, const uint8_t* expo, const double* coef,
-                    const double* lo, const double* hi, double* trace) {
+                    const double* lo, const double* hi, double* trace, int contractor) {
   KEEP_CALLER_MODE;
   osys s = make_sys(n, term_off, expo, coef);
   ival X[OR_MAX_N], Xn[OR_MAX_N];
@@ -599,19 +660,19 @@ int oracle_hs_trace(int n, const int32_t* term_off, const uint8_t* expo, const d
   memset(trace, 0, sizeof(double) * (size_t)(6 * n * n + 8 * n + 4));
   int u = 0;
   g_trace = trace;
-  int st = hs_step(&s, X, Xn, &u);
+  int st = hs_step(&s, X, Xn, &u, contractor);
   g_trace = NULL;
   return st;
 }
 
 int oracle_hs(int n, const int32_t* term_off, const uint8_t* expo, const double* coef,
-              const double* lo, const double* hi, double* out_lo, double* out_hi, int* unique) {
+              const double* lo, const double* hi, double* out_lo, double* out_hi, int* unique, int contractor) {
   KEEP_CALLER_MODE;
   osys s = make_sys(n, term_off, expo, coef);
   ival X[OR_MAX_N], Xn[OR_MAX_N];
   for (int k = 0; k < n; ++k) X[k] = iv(lo[k], hi[k]);
   int u = 0;
-  int st = hs_step(&s, X, Xn, &u);
+  int st = hs_step(&s, X, Xn, &u, contractor);
   if (st == HS_DONE)
     for (int k = 0; k < n; ++k) {
       out_lo[k] = Xn[k].lo;
@@ -631,6 +692,8 @@ typedef struct {
   int32_t max_recontract;
   double recontract_ratio;
   double hs_max_width;
+  int32_t contractor; /* OR_CONTRACT_HS or OR_CONTRACT_KRAWCZYK */
+  int32_t inclusion;  /* 0 natural extension; 1 also the mean-value form */
 } oparams;
 
 typedef struct {
@@ -741,6 +804,8 @@ static int valid_input(int n, const int32_t* term_off, const uint8_t* expo, cons
   if (p->max_recontract < 1) return 0;
   if (!(p->recontract_ratio >= 0) || !(p->recontract_ratio <= 1)) return 0;
   if (isnan(p->hs_max_width)) return 0;
+  if (p->contractor != OR_CONTRACT_HS && p->contractor != OR_CONTRACT_KRAWCZYK) return 0;
+  if (p->inclusion != 0 && p->inclusion != 1) return 0;
   return 1;
 }
 
@@ -786,6 +851,27 @@ static int step_box(const osys* s, const oparams* p, const obox* b, ostack* st, 
       S->excluded_eval++;
       return OR_OK;
     }
+    /* Mean-value form (a centred inclusion, Sec. 2.2): by the mean value
+     * theorem f_i(X) lies in F_i(x) + sum_k J_ik(X) (X_k - x_k), x = mid X;
+     * evaluated as written, the sum over k ascending added to F_i(x) term by
+     * term.  The box holds no root if some component excludes 0. */
+    if (p->inclusion == 1) {
+      ival Xc[OR_MAX_N], D[OR_MAX_N];
+      for (int k = 0; k < n; ++k) {
+        double m = i_mid(b->X[k]);
+        Xc[k] = iv(m, m);
+        D[k] = i_sub(b->X[k], Xc[k]);
+      }
+      for (int i = 0; i < n && !excluded; ++i) {
+        ival acc = eval_f(s, i, Xc);
+        for (int k = 0; k < n; ++k) acc = i_add(acc, i_mul(eval_df(s, i, k, b->X), D[k]));
+        if (acc.lo > 0 || acc.hi < 0) excluded = 1;
+      }
+      if (excluded) {
+        S->excluded_eval++;
+        return OR_OK;
+      }
+    }
   }
 
   /* Contraction (Alg. 3), unless the box is wider than hs_max_width. */
@@ -793,7 +879,7 @@ static int step_box(const osys* s, const oparams* p, const obox* b, ostack* st, 
   ival Xn[OR_MAX_N];
   int u = 0;
   int hs = HS_SKIPPED;
-  if (!(w > p->hs_max_width)) hs = hs_step(s, b->X, Xn, &u);
+  if (!(w > p->hs_max_width)) hs = hs_step(s, b->X, Xn, &u, p->contractor);
   if (hs == HS_EMPTY) {
     S->excluded_hs++;
     return OR_OK;
@@ -901,9 +987,10 @@ int oracle_solve(int n, const int32_t* term_off, const uint8_t* expo, const doub
                  const double* lo, const double* hi, double tol, int64_t max_boxes,
                  int32_t split_mode, int32_t max_recontract, double recontract_ratio,
                  double hs_max_width, double* out_lo, double* out_hi, uint8_t* out_tag,
-                 int64_t cap, int64_t* n_out, int64_t* stats_out, int order, uint64_t seed) {
+                 int64_t cap, int64_t* n_out, int64_t* stats_out, int order, uint64_t seed, int32_t contractor,
+                 int32_t inclusion) {
   KEEP_CALLER_MODE;
-  oparams p = {tol, max_boxes, split_mode, max_recontract, recontract_ratio, hs_max_width};
+  oparams p = {tol, max_boxes, split_mode, max_recontract, recontract_ratio, hs_max_width, contractor, inclusion};
   ostats S;
   memset(&S, 0, sizeof S);
   *n_out = 0;
@@ -990,9 +1077,10 @@ int oracle_round(int n, const int32_t* term_off, const uint8_t* expo, const doub
                  const double* lo, const double* hi, const uint32_t* rec, double tol, int32_t split_mode,
                  int32_t max_recontract, double recontract_ratio, double hs_max_width, double* child_lo,
                  double* child_hi, uint32_t* child_rec, int64_t child_cap, int64_t* n_child, double* emit_lo,
-                 double* emit_hi, uint8_t* emit_tag, int64_t emit_cap, int64_t* n_emit, int64_t* stats_out) {
+                 double* emit_hi, uint8_t* emit_tag, int64_t emit_cap, int64_t* n_emit, int64_t* stats_out,
+                 int32_t contractor, int32_t inclusion) {
   KEEP_CALLER_MODE;
-  oparams p = {tol, 1, split_mode, max_recontract, recontract_ratio, hs_max_width};
+  oparams p = {tol, 1, split_mode, max_recontract, recontract_ratio, hs_max_width, contractor, inclusion};
   ostats S;
   memset(&S, 0, sizeof S);
   *n_child = 0;

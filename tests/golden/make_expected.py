@@ -6,6 +6,7 @@ are stored as hex strings (float.hex) so that they round-trip exactly.
 
     python tests/golden/make_expected.py dense6_s0 banded12_s0 ...
     python tests/golden/make_expected.py served_s0
+    python tests/golden/make_expected.py dense6_s0_krawczyk dense6_s0_meanvalue ...
 
 Cases other than the first four store no proof chains (computing them solves
 the system a second time).  ``served_s0`` stores the first SERVED_PICK banded
@@ -36,6 +37,11 @@ CASES = {
 for _k in (2, 3, 4):
     CASES[f"dense6_s{_k}"] = (lambda k: lambda: (W.dense_planted(k), {"max_boxes": 50_000_000}))(_k)
     CASES[f"banded12_s{_k}"] = (lambda k: lambda: (W.banded(k), {"max_boxes": 50_000_000}))(_k)
+# the Krawczyk contractor and the mean-value exclusion test on seed 0
+for _k in ("dense6", "banded12"):
+    _mk = W.dense_planted if _k == "dense6" else W.banded
+    CASES[f"{_k}_s0_krawczyk"] = (lambda mk: lambda: (mk(0), {"contractor": 1, "max_boxes": 50_000_000}))(_mk)
+    CASES[f"{_k}_s0_meanvalue"] = (lambda mk: lambda: (mk(0), {"inclusion": 1, "max_boxes": 50_000_000}))(_mk)
 WITH_CHAINS = {"dense6_s0", "dense6_s1", "banded12_s0", "banded12_s1"}
 SERVED_PICK = 6
 SERVED_SCAN = 40

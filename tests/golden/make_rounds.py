@@ -1,7 +1,9 @@
 """Writes the oracle's per-round kept-box counts for the paper's worked examples
 (all coordinates bisected, no contraction) to tests/golden/oracle_rounds.json.
-Calls only the CPU oracle.   python tests/golden/make_rounds.py [last_round]"""
-import itertools
+Calls only the CPU oracle: the kept boxes of round r are the children of the
+kept boxes of round r-1 (each bisected in every coordinate, Alg. 2) that pass
+the exclusion test (Def. 2), tested in C by oracle.exclusion_keep; the last
+round is only counted.   python tests/golden/make_rounds.py [last_round]"""
 import json
 import os
 import sys
@@ -15,28 +17,38 @@ import oracle  # noqa: E402
 from tests.golden_systems import load  # noqa: E402
 
 
-def rounds(name, last):
+def children(lo, hi):
+    """All 2^n children of each box (exact midpoints: the boxes are dyadic)."""
+    m, n = lo.shape
+    mid = (lo + hi) / 2
+    bits = ((np.arange(1 << n)[:, None] >> np.arange(n)[None, :]) & 1).astype(bool)  # [2^n, n]
+    clo = np.where(bits[None], mid[:, None], lo[:, None]).reshape(-1, n)
+    chi = np.where(bits[None], hi[:, None], mid[:, None]).reshape(-1, n)
+    return clo, chi
+
+
+def rounds(name, last, chunk=256):
     s, _ = load(name)
-    level = [(s.lo.copy(), s.hi.copy())]
+    lo, hi = s.lo[None].copy(), s.hi[None].copy()
     out = {1: 1}
     for rnd in range(2, last + 1):
-        nxt = []
-        for lo, hi in level:
-            mid = (lo + hi) / 2  # exact: dyadic boxes
-            for bits in itertools.product((0, 1), repeat=s.n):
-                b = np.array(bits, dtype=bool)
-                clo, chi = np.where(b, mid, lo), np.where(b, hi, mid)
-                flo, fhi = oracle.eval_F(s, clo, chi)
-                if np.all(flo <= 0) and np.all(fhi >= 0):
-                    nxt.append((clo, chi))
-        level = nxt
-        out[rnd] = len(level)
-        print(name, rnd, len(level), flush=True)
+        kept_lo, kept_hi, count = [], [], 0
+        for a in range(0, lo.shape[0], chunk):
+            clo, chi = children(lo[a:a + chunk], hi[a:a + chunk])
+            keep = oracle.exclusion_keep(s, clo, chi)
+            count += int(keep.sum())
+            if rnd < last:
+                kept_lo.append(clo[keep])
+                kept_hi.append(chi[keep])
+        out[rnd] = count
+        print(name, rnd, count, flush=True)
+        if rnd < last:
+            lo, hi = np.concatenate(kept_lo), np.concatenate(kept_hi)
     return out
 
 
 if __name__ == "__main__":
-    last = int(sys.argv[1]) if len(sys.argv) > 1 else 4
+    last = int(sys.argv[1]) if len(sys.argv) > 1 else 5
     res = {name: rounds(name, last) for name in ("katsura8", "noon9", "kinema")}
     with open(os.path.join(HERE, "oracle_rounds.json"), "w") as fh:
         json.dump(res, fh, indent=1)
