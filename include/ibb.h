@@ -41,7 +41,8 @@ extern "C" {
 #define IBB_ERR_OUTPUT_CAPACITY (-3) /* more boxes than `cap`; *n_out = required count */
 #define IBB_ERR_QUEUE_OVERFLOW (-4)  /* a tree level exceeded the frontier capacity    */
 #define IBB_ERR_NO_MEMORY (-5)       /* device or host allocation failed               */
-#define IBB_ERR_DEVICE (-6)          /* a HIP runtime call failed                      */
+#define IBB_ERR_DEVICE (-6)          /* a HIP runtime call failed, or a search kernel
+                                        found its FP64 rounding mode changed          */
 #define IBB_ERR_UNSUPPORTED (-7)     /* valid request outside this build's limits      */
 #define IBB_ERR_TIMEOUT (-8)         /* a device-side wait exceeded its time limit     */
 #define IBB_ERR_WORKSPACE_LIMIT (-9) /* ibb_solve_noalloc: workspace above its maximum */
@@ -68,9 +69,31 @@ extern "C" {
 #define IBB_SCHEDULE_QUEUE 0
 #define IBB_SCHEDULE_LEVELS 1
 /* IBB_SCHEDULE_AUTO (default): per system shape (n, terms, derivative terms,
- * split mode) the context times the search kernel once with each schedule,
+ * split mode, contractor, inclusion) the context times the search kernel once
+ * with each schedule,
  * then keeps the faster one.  Results do not depend on the choice. */
 #define IBB_SCHEDULE_AUTO 2
+
+/* Contraction step applied to the boxes that pass the exclusion test.
+ * IBB_CONTRACT_HS: the Hansen-Sengupta step (Sec. 2.3 eq 17-22; Alg. 3):
+ * X'_i = X_i meets x_i - [g_i + sum_{j<i} P_ij (X'_j - x_j) + sum_{j>i}
+ * P_ij (X_j - x_j)] / P_ii, component after component; unique root when
+ * every Y_i lies inside the interior of X_i.  IBB_CONTRACT_KRAWCZYK: the
+ * Krawczyk operator (eq 15) K(X) = x - g + (I - P)(X - x) with g = Y F(x),
+ * P = Y J(X) (the same preconditioner Y), X' = X meets K(X) (eq 16); unique
+ * root when K(X) lies inside the interior of X. */
+#define IBB_CONTRACT_HS 0
+#define IBB_CONTRACT_KRAWCZYK 1
+
+/* Inclusion of F used by the exclusion test (Def. 2).  IBB_INCLUDE_NATURAL:
+ * the natural interval extension (Def. 1).  IBB_INCLUDE_MEAN_VALUE: a box the
+ * natural extension keeps (and that is not proven to hold a root) is also
+ * tested with the mean-value form F_i(x) + sum_k J_ik(X) (X_k - x_k), x the
+ * midpoint (one of the tighter inclusion strategies of Sec. 2.2); it is
+ * discarded when some component excludes 0 (counted as excluded_eval).  The
+ * box lists differ from the natural extension's. */
+#define IBB_INCLUDE_NATURAL 0
+#define IBB_INCLUDE_MEAN_VALUE 1
 
 /* A square polynomial system in sparse monomial form (Sec. 2.1).
  * Equation i owns terms term_off[i] .. term_off[i+1]-1, in the order given;
@@ -93,6 +116,8 @@ typedef struct {
   double recontract_ratio; /* re-contract when the width shrank to <= ratio * width (0.5) */
   double hs_max_width;     /* skip the contraction on boxes wider than this (+inf)       */
   int32_t schedule;        /* IBB_SCHEDULE_AUTO (default), _QUEUE or _LEVELS             */
+  int32_t contractor;      /* IBB_CONTRACT_HS (default) or IBB_CONTRACT_KRAWCZYK         */
+  int32_t inclusion;       /* IBB_INCLUDE_NATURAL (default) or IBB_INCLUDE_MEAN_VALUE     */
   int32_t reserved;        /* must be 0                                                  */
 } ibb_params;
 
@@ -185,7 +210,14 @@ void ibb_batch_plan_destroy(ibb_batch_plan* plan);
  *                    default, as many as registers and LDS allow; larger
  *                    values are clamped to that);
  *   tuned, ms        set by ibb_batch_tune: 1 and the measured device time of
- *                    the class's sample with this configuration (else 0, 0).
+ *                    the class's sample with this configuration (else 0, 0);
+ *   front_per_member set by ibb_batch_tune: the widest tree level of the
+ *                    class's sample launch divided by its members (0 = not
+ *                    measured).  Queue sizes: when every class of a batch has
+ *                    it, the batch's frontier is sized to 1.5 times the widest
+ *                    launch's sum of its members' values (else a quarter of
+ *                    the members' node budgets), and never below what an
+ *                    earlier batch on the context needed.
  * Each box's fate depends on the box alone, so results, counters and statuses
  * are the same under every configuration (the batched analogue of the
  * autotuner's schedule choice for one system). */
@@ -195,14 +227,15 @@ typedef struct ibb_batch_config {
   int32_t blocks_per_cu;
   int32_t tuned;
   double ms;
+  double front_per_member;
 } ibb_batch_config;
 
 /* Current configuration of class cls (0..3) into *out.  IBB_ERR_INVALID_ARG
  * for a bad class or null pointer. */
 int ibb_batch_get_config(ibb_ctx* ctx, int32_t cls, ibb_batch_config* out);
 
-/* Replace the configuration of class cls (tuned and ms are ignored and
- * cleared).  IBB_ERR_INVALID_ARG unless lanes is a power of two with
+/* Replace the configuration of class cls (tuned, ms and front_per_member
+ * are ignored and cleared).  IBB_ERR_INVALID_ARG unless lanes is a power of two with
  * 2 << cls <= lanes <= 16, 1 <= tiles_per_claim <= 16 and blocks_per_cu >= 0. */
 int ibb_batch_set_config(ibb_ctx* ctx, int32_t cls, const ibb_batch_config* cfg);
 
@@ -221,40 +254,63 @@ int ibb_batch_tune(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const dou
 
 /* ---- serving: continuous batching of solves on one device ----
  * Requests are queued by ibb_server_submit (the system is copied).  Each call
- * of ibb_server_step (1) admits queued requests while a device slot is free
- * and the size bucket's frontier still has `reserve_per_solve` boxes
- * unreserved -- admission by the device memory the request's box queue needs;
- * (2) runs `levels_per_quantum` tree levels of every admitted solve together,
- * new arrivals joining solves already on the device; (3) harvests the solves
- * that ran out of boxes.  A solve keeps its boxes resident on the device until
- * it finishes, and its result is identical to ibb_solve on it alone.
- * Only IBB_SPLIT_WIDEST is served. */
+ * of ibb_server_step
+ *   (1) waits for the device pass the previous call enqueued and harvests the
+ *       solves that ran out of boxes (their ids become available from
+ *       ibb_server_finished, their results from ibb_server_poll);
+ *   (2) admits queued requests, in arrival order, while a device slot is free
+ *       and the request's reservation fits the device pool: a request
+ *       reserves frontier boxes for itself, reserve_per_solve for every 64
+ *       bisections its tree needs at least (each coordinate halved from its
+ *       initial width down to tol), at most max_boxes + 1, and the bytes of
+ *       two levels of that many boxes of its size bucket; the admitted
+ *       requests of a call are uploaded with one copy and one kernel and join
+ *       the solves already on the device;
+ *   (3) makes room for the next levels of each size bucket: its frontier grows
+ *       while all bucket frontiers together stay within pool_bytes; when they
+ *       cannot, the solves holding the most boxes beyond their reservation
+ *       are failed with IBB_ERR_QUEUE_OVERFLOW, alone (their boxes are dropped,
+ *       the other solves go on);
+ *   (4) enqueues one pass of `levels_per_quantum` tree levels of every bucket
+ *       and returns without waiting for it, so that host work between calls
+ *       overlaps the device's.
+ * A solve keeps its boxes resident on the device until it finishes, and its
+ * result is identical to ibb_solve on it alone.  Only IBB_SPLIT_WIDEST is
+ * served. */
 typedef struct {
-  int32_t max_slots;          /* solves resident on the device at once (256)    */
-  int64_t frontier_cap;       /* boxes per size bucket's frontier (2^20); grows */
-  int64_t reserve_per_solve;  /* frontier boxes reserved per admitted solve     */
-  int32_t levels_per_quantum; /* tree levels per device pass (8)                */
-  int32_t out_cap_per_solve;  /* output boxes per solve (1024)                  */
+  int32_t max_slots;          /* solves resident on the device at once (256)     */
+  int64_t frontier_cap;       /* initial boxes per size bucket's frontier (2^20) */
+  int64_t reserve_per_solve;  /* frontier boxes reserved per 64 bisections (2^14) */
+  int32_t levels_per_quantum; /* tree levels per device pass (8)                 */
+  int32_t out_cap_per_solve;  /* output boxes per solve (1024)                   */
+  int64_t pool_bytes;         /* device bytes for all bucket frontiers (8 GiB)   */
 } ibb_server_config;
 
 typedef struct ibb_server ibb_server;
 
 void ibb_server_config_default(ibb_server_config* cfg);
-/* Allocates the server's device state on the context's GPU (cfg may be NULL). */
+/* Allocates the server's device state on the context's GPU (cfg may be NULL).
+ * IBB_ERR_INVALID_ARG if the four initial bucket frontiers exceed pool_bytes. */
 int ibb_server_create(ibb_ctx* ctx, const ibb_server_config* cfg, ibb_server** out);
+/* Waits for the device, frees the server and every request it holds. */
 void ibb_server_destroy(ibb_server* server);
 /* Queues a request; returns its id (>= 0) or a negative status. */
 int64_t ibb_server_submit(ibb_server* server, const ibb_system* sys, const double* lo, const double* hi,
                           const ibb_params* params);
-/* One scheduling round (admit, one quantum, harvest); returns the number of
- * requests finished in this round, or a negative status. */
+/* One scheduling round (see above); returns the number of requests harvested
+ * in this round, or a negative status. */
 int ibb_server_step(ibb_server* server);
+/* Copies up to cap ids of requests harvested since the previous call (in
+ * harvest order) to ids and forgets them; returns how many were copied. */
+int64_t ibb_server_finished(ibb_server* server, int64_t* ids, int64_t cap);
 /* Result of a finished request (then forgotten): IBB_OK with the sorted boxes
- * as in ibb_solve, *status the request's own status; returns 1 while the
- * request is queued or running. */
+ * as in ibb_solve, *status the request's own status (IBB_OK, IBB_ERR_BUDGET,
+ * IBB_ERR_OUTPUT_CAPACITY, IBB_ERR_QUEUE_OVERFLOW); returns 1 while the request
+ * is queued or running. */
 int ibb_server_poll(ibb_server* server, int64_t id, double* out_lo, double* out_hi, uint8_t* out_tag,
                     int64_t cap, int64_t* n_out, int32_t* status, ibb_stats* stats);
-/* Removes a request that has not been admitted yet. */
+/* Removes a request that has not been admitted yet (IBB_ERR_UNSUPPORTED once
+ * it is on the device). */
 int ibb_server_cancel(ibb_server* server, int64_t id);
 /* Requests waiting for admission and requests on the device. */
 int ibb_server_pending(ibb_server* server, int64_t* queued, int64_t* active);
@@ -342,6 +398,34 @@ int ibb_round(ibb_ctx* ctx, const ibb_system* sys, const ibb_params* params, int
               double* child_hi, uint32_t* child_rec, int64_t child_cap, int64_t* n_child,
               double* emit_lo, double* emit_hi, uint8_t* emit_tag, int64_t emit_cap,
               int64_t* n_emit, ibb_stats* stats);
+
+/* ---- backtracking merge (Alg. 5) ----
+ * Merges output boxes into cells of the all-coordinate bisection grid of the
+ * initial box X0 = [x0_lo, x0_hi] (Alg. 2): cell j = (j_0..j_{n-1}) of round k
+ * covers, in coordinate i, [a + j_i (b - a) / 2^k, a + (j_i + 1) (b - a) / 2^k]
+ * with [a, b] = [x0_lo[i], x0_hi[i]].  Each of the m boxes (host, row-major
+ * [m][n], inside X0) first becomes the round-`level` cells it meets: per
+ * coordinate the cells whose interior meets the box's interior (a degenerate
+ * coordinate: the cell [B_j, B_{j+1}) holding the point, the last cell
+ * closed).  Then, round after round, each cell is replaced by the cell of the
+ * previous round it was split from (Alg. 5: j_i -> floor(j_i / 2)) and the
+ * duplicates are dropped.  Outputs (host, caller-allocated): counts[k] =
+ * distinct cells at round k for k = 0..level ([level + 1]); out_cells = the
+ * distinct round-`out_level` cells as index rows [cap][n], sorted
+ * lexicographically, *n_out their number.  The paper reads the isolated
+ * roots off the first round, from the finest, whose count equals the next
+ * coarser round's (Tab. 3, 6, 8).  Grid comparisons are exact.  Errors:
+ * IBB_ERR_INVALID_ARG (n outside 1..16, level outside 0..IBB_BACKTRACK_MAX_LEVEL,
+ * out_level > level, X0 bounds not finite, not lo < hi, or nonzero with
+ * magnitude outside [2^-500, 2^40], a box not inside X0), IBB_ERR_UNSUPPORTED
+ * (more than IBB_BACKTRACK_MAX_CELLS round-`level` cells), IBB_ERR_OUTPUT_CAPACITY
+ * (*n_out > cap; counts are still written), IBB_ERR_NO_MEMORY.  Host only,
+ * no context needed. */
+#define IBB_BACKTRACK_MAX_LEVEL 50
+#define IBB_BACKTRACK_MAX_CELLS (1 << 21)
+int ibb_backtrack(int32_t n, const double* x0_lo, const double* x0_hi, int64_t m, const double* lo,
+                  const double* hi, int32_t level, int64_t* counts, int32_t out_level, int64_t* out_cells,
+                  int64_t cap, int64_t* n_out);
 
 /* Diagnostics: run the search step on the single box [lo, hi] (one tree
  * level) and copy its intermediates to `dump` (host, >= 6n^2 + 8n + 4

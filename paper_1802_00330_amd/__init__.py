@@ -27,6 +27,8 @@ ERR_NO_MEMORY, ERR_DEVICE, ERR_UNSUPPORTED, ERR_TIMEOUT = -5, -6, -7, -8
 ERR_WORKSPACE_LIMIT = -9
 NOALLOC_WORKSPACE_BYTES = 64 << 20
 SPLIT_WIDEST, SPLIT_ALL = 0, 1
+CONTRACT_HS, CONTRACT_KRAWCZYK = 0, 1
+INCLUDE_NATURAL, INCLUDE_MEAN_VALUE = 0, 1
 UNDECIDED, UNIQUE = 0, 1
 MAX_N = 16
 
@@ -39,7 +41,7 @@ EXPORTS = ("ibb_ctx_create", "ibb_ctx_destroy", "ibb_strerror", "ibb_params_defa
            "ibb_server_create", "ibb_server_destroy", "ibb_server_submit", "ibb_server_step", "ibb_server_poll",
            "ibb_server_cancel", "ibb_server_pending", "ibb_round", "ibb_batch_plan_create", "ibb_batch_plan_run",
            "ibb_batch_plan_destroy", "ibb_batch_get_config", "ibb_batch_set_config", "ibb_batch_tune",
-           "ibb_solve_noalloc")
+           "ibb_solve_noalloc", "ibb_server_finished", "ibb_backtrack")
 
 
 class IbbSystem(C.Structure):
@@ -49,18 +51,19 @@ class IbbSystem(C.Structure):
 class IbbParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_boxes", C.c_int64), ("split_mode", C.c_int32),
                 ("max_recontract", C.c_int32), ("recontract_ratio", C.c_double),
-                ("hs_max_width", C.c_double), ("schedule", C.c_int32), ("reserved", C.c_int32)]
+                ("hs_max_width", C.c_double), ("schedule", C.c_int32), ("contractor", C.c_int32),
+                ("inclusion", C.c_int32), ("reserved", C.c_int32)]
 
 
 class IbbServerConfig(C.Structure):
     _fields_ = [("max_slots", C.c_int32), ("frontier_cap", C.c_int64), ("reserve_per_solve", C.c_int64),
-                ("levels_per_quantum", C.c_int32), ("out_cap_per_solve", C.c_int32)]
+                ("levels_per_quantum", C.c_int32), ("out_cap_per_solve", C.c_int32), ("pool_bytes", C.c_int64)]
 
 
 class IbbBatchConfig(C.Structure):
     """Launch configuration of one lane-count class of batch members (ibb_batch_config)."""
     _fields_ = [("lanes", C.c_int32), ("tiles_per_claim", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("tuned", C.c_int32), ("ms", C.c_double)]
+                ("tuned", C.c_int32), ("ms", C.c_double), ("front_per_member", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -117,6 +120,9 @@ def load_library(path: str = LIB_PATH):
     L.ibb_server_poll.argtypes = [p, i64, p, p, p, i64, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                   C.POINTER(IbbStats)]
     L.ibb_server_cancel.restype, L.ibb_server_cancel.argtypes = C.c_int, [p, i64]
+    L.ibb_server_finished.restype, L.ibb_server_finished.argtypes = i64, [p, p, i64]
+    L.ibb_backtrack.restype = C.c_int
+    L.ibb_backtrack.argtypes = [i32, p, p, i64, p, p, i32, p, i32, p, i64, C.POINTER(C.c_int64)]
     L.ibb_server_pending.restype = C.c_int
     L.ibb_server_pending.argtypes = [p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.ibb_debug_step.restype = C.c_int
@@ -186,9 +192,10 @@ class _SysRef:
 
 def make_params(tol: float, max_boxes: int = 100_000_000, split_mode: int = SPLIT_WIDEST,
                 max_recontract: int = 16, recontract_ratio: float = 0.5,
-                hs_max_width: float = float("inf"), schedule: int = 2) -> IbbParams:
+                hs_max_width: float = float("inf"), schedule: int = 2, contractor: int = CONTRACT_HS,
+                inclusion: int = INCLUDE_NATURAL) -> IbbParams:
     return IbbParams(float(tol), int(max_boxes), int(split_mode), int(max_recontract),
-                     float(recontract_ratio), float(hs_max_width), int(schedule), 0)
+                     float(recontract_ratio), float(hs_max_width), int(schedule), int(contractor), int(inclusion), 0)
 
 
 @dataclass
@@ -348,6 +355,31 @@ def ibb_debug_step(ctx: Context, s, lo, hi, params: Optional[IbbParams] = None) 
     if st != OK:
         raise RuntimeError(f"ibb_debug_step: {ibb_strerror(st)}")
     return dump
+
+
+def ibb_backtrack(lo, hi, x0_lo, x0_hi, level: int, out_level: Optional[int] = None):
+    """Backtracking merge (Alg. 5) of boxes lo/hi [m, n] inside the initial box
+    x0: returns (counts [level + 1], cells of round out_level [c, n] int64)."""
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    x0_lo = np.ascontiguousarray(x0_lo, dtype=np.float64)
+    x0_hi = np.ascontiguousarray(x0_hi, dtype=np.float64)
+    n = int(x0_lo.size)
+    m = int(lo.size // n) if n else 0
+    out_level = level if out_level is None else out_level
+    counts = np.zeros(level + 1, dtype=np.int64)
+    cap = 1024
+    while True:
+        cells = np.zeros((cap, n), dtype=np.int64)
+        nout = C.c_int64(0)
+        st = load_library().ibb_backtrack(n, _ptr(x0_lo), _ptr(x0_hi), m, _ptr(lo), _ptr(hi), int(level),
+                                          _ptr(counts), int(out_level), _ptr(cells), int(cap), C.byref(nout))
+        if st == ERR_OUTPUT_CAPACITY:
+            cap = int(nout.value)
+            continue
+        if st != OK:
+            raise RuntimeError(f"ibb_backtrack: {ibb_strerror(st)}")
+        return counts.copy(), cells[: int(nout.value)].copy()
 
 
 @dataclass
@@ -552,6 +584,28 @@ class Server:
         k = int(m.value) if status.value == OK else 0
         stats = {f: int(getattr(st_, f)) for f in STATS_FIELDS}
         return Result(int(status.value), olo[:k].copy(), ohi[:k].copy(), otag[:k].copy(), stats)
+
+    def finished(self, cap: int = 4096) -> list:
+        """Ids harvested since the previous call (ibb_server_finished)."""
+        out = []
+        buf = np.zeros(cap, dtype=np.int64)
+        while True:
+            m = int(load_library().ibb_server_finished(self.handle, _ptr(buf), int(cap)))
+            if m < 0:
+                raise RuntimeError(f"ibb_server_finished: {ibb_strerror(m)}")
+            out.extend(int(v) for v in buf[:m])
+            if m < cap:
+                return out
+
+    def cancel(self, rid: int) -> bool:
+        """Removes a request not admitted yet; False once it is on the device."""
+        st = load_library().ibb_server_cancel(self.handle, int(rid))
+        if st == OK:
+            del self.n[rid]
+            return True
+        if st == ERR_UNSUPPORTED:
+            return False
+        raise RuntimeError(f"ibb_server_cancel: {ibb_strerror(st)}")
 
     def pending(self):
         q, a = C.c_int64(0), C.c_int64(0)

@@ -19,7 +19,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-value", "-Wno-unused-result",
 ]
-SOURCES = ["kernels.hip", "api.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "backtrack.cpp"]
 
 
 # Kernels that run a whole search in one persistent launch.

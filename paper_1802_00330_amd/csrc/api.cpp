@@ -19,7 +19,7 @@
 namespace ibb {
 // kernels.hip
 size_t scratch_bytes(int G, int jn, int rs);
-const void* solve_kernel_ptr(int G, bool multi);
+const void* solve_kernel_ptr(int G, bool multi, bool var);
 hipError_t launch_prep(hipStream_t s, uint64_t* blobs, const long long* blob_off, int B);
 hipError_t launch_batch_init(hipStream_t s, Ctrl* c, double* front0, uint32_t* meta0, uint32_t* sys0,
                              const double* lo, const double* hi, const int* bucket, int m, int G, const int* nsys,
@@ -37,7 +37,7 @@ hipError_t launch_sort(hipStream_t s, const double* box, const uint32_t* tag, co
                        long long grid_elems);
 hipError_t launch_finalize(hipStream_t s, const Ctrl* c, long long out_cap, long long* info,
                            const long long* depth_counts, int level_cap);
-const void* queue_kernel_ptr(int G);
+const void* queue_kernel_ptr(int G, bool var);
 hipError_t launch_queue_init(hipStream_t s, unsigned long long* seq, long long cap, Ctrl* c, long long* level_sizes,
                              int level_cap);
 hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, long long count, unsigned long long v);
@@ -94,6 +94,8 @@ int validate(const ibb_system* s, const double* lo, const double* hi, const ibb_
   if (std::isnan(p->hs_max_width)) return IBB_ERR_INVALID_ARG;
   if (p->schedule != IBB_SCHEDULE_QUEUE && p->schedule != IBB_SCHEDULE_LEVELS && p->schedule != IBB_SCHEDULE_AUTO)
     return IBB_ERR_INVALID_ARG;
+  if (p->contractor != IBB_CONTRACT_HS && p->contractor != IBB_CONTRACT_KRAWCZYK) return IBB_ERR_INVALID_ARG;
+  if (p->inclusion != IBB_INCLUDE_NATURAL && p->inclusion != IBB_INCLUDE_MEAN_VALUE) return IBB_ERR_INVALID_ARG;
   if (p->reserved != 0) return IBB_ERR_INVALID_ARG;
   if (T > IBB_MAX_TERMS) return IBB_ERR_UNSUPPORTED;
   if (p->max_recontract > 255) return IBB_ERR_UNSUPPORTED;
@@ -299,21 +301,22 @@ int ensure_pinned(ibb_ctx* ctx, size_t need) {
 }
 
 // Workgroups of a persistent launch that are resident on one CU at once.
-// The occupancy query alone over-promises near the LDS limit (measured on
-// gfx950: three workgroups of 53,952 B were reported to fit the 160 KiB of a
-// CU, two were resident); LDS is therefore also counted in granules.
+// The occupancy query alone over-promises near the LDS limit.  Measured on
+// gfx950 (a probe that launches k workgroups per CU with L bytes of LDS each
+// and waits, bounded, until all are present; L swept in 256-byte steps for
+// k = 2..6): all k were resident exactly while k * ceil(L / 1280) <= 128,
+// i.e. the CU's 160 KiB of LDS is allocated in 128 granules of 1280 bytes
+// (largest resident L: 81,920 / 53,589 / 40,960 / 32,000 / 26,794 bytes for
+// k = 2..6; smallest not resident: 82,176 / 53,845 / 41,216 / 32,256 /
+// 27,050).
 int resident_per_cu(ibb_ctx* ctx, const void* fn, int threads, size_t lds) {
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) return 0;
-  // The runtime's figure can exceed what becomes resident on a 160 KiB CU:
-  // workgroups needing 3 x 54,272 and 5 x 32,256 bytes (512-byte granules)
-  // were not all resident at once (a level's grid barrier waited in vain),
-  // while 5 x 31,744 = 158,720 bytes were.  Persistent launches therefore
-  // count 512-byte granules against the CU's LDS less 5 KiB.
-  const size_t granule = 512, reserve = 5120;
-  const size_t rounded = (lds + granule - 1) / granule * granule;
-  if (rounded > 0 && ctx->lds_per_cu > reserve)
-    per_cu = std::min<int>(per_cu, (int)((ctx->lds_per_cu - reserve) / rounded));
+  const size_t granules = 128, granule = ctx->lds_per_cu / granules;
+  if (lds > 0 && granule > 0) {
+    const size_t need = (lds + granule - 1) / granule;
+    per_cu = std::min<int>(per_cu, (int)(granules / need));
+  }
   return per_cu;
 }
 
@@ -382,6 +385,8 @@ int launch_search(ibb_ctx* ctx, const Compiled& c, const ibb_params* p, char* ws
   a.max_boxes = max_boxes;
   a.split_mode = p->split_mode;
   a.max_rc = p->max_recontract;
+  a.contractor = p->contractor;
+  a.inclusion = p->inclusion;
   a.timeout_ticks = ctx->clock_khz * 1000LL * 20;  // 20 s per barrier wait
   a.max_levels = max_levels;
   a.dbg = d_dbg;
@@ -394,7 +399,8 @@ int launch_search(ibb_ctx* ctx, const Compiled& c, const ibb_params* p, char* ws
   a.stage_box = reinterpret_cast<double*>(ws + L.stage_box);
   a.stage_meta = reinterpret_cast<uint32_t*>(ws + L.stage_meta);
 
-  const void* fn = queue ? queue_kernel_ptr(G) : solve_kernel_ptr(G, false);
+  const bool var = p->contractor != IBB_CONTRACT_HS || p->inclusion != IBB_INCLUDE_NATURAL;
+  const void* fn = queue ? queue_kernel_ptr(G, var) : solve_kernel_ptr(G, false, var);
   const size_t tbytes = (table_lds_bytes(n, c.T, c.TD) + 15) & ~size_t(15);
   Geometry geo;
   {
@@ -438,7 +444,8 @@ int resolve_schedule(ibb_ctx* ctx, const Compiled& c, const ibb_params* p) {
     }
     ctx->tune_pending = false;
   }
-  const auto key = std::make_tuple(c.n, c.T, c.TD, p->split_mode);
+  // shape key: size, terms, derivative terms, and the split, contractor and inclusion (their kernels differ)
+  const auto key = std::make_tuple(c.n, c.T, c.TD, p->split_mode | (p->contractor << 2) | (p->inclusion << 3));
   auto it = ctx->tune.find(key);
   if (it == ctx->tune.end()) it = ctx->tune.emplace(key, std::array<float, 2>{-1.0f, -1.0f}).first;
   int sched = p->schedule;
@@ -621,7 +628,8 @@ int batch_prepare(int B, const ibb_system* systems, const double* lo, const doub
     h.words += comp[b].blob.size();
     h.nsys[b] = comp[b].n;
     const ibb_params& p = params[b];
-    h.sp[b] = SysParams{p.tol, p.recontract_ratio, p.hs_max_width, p.max_boxes, p.split_mode, p.max_recontract};
+    h.sp[b] = SysParams{p.tol, p.recontract_ratio, p.hs_max_width, p.max_boxes, p.split_mode, p.max_recontract,
+                         p.contractor, p.inclusion};
     // the member runs with the lane count its class is configured for
     buckets[lanes_class(cfg[lanes_class(comp[b].G)].lanes)].push_back(b);
   }
@@ -725,7 +733,7 @@ int batch_enqueue(ibb_ctx* ctx, const BatchHost& h, char* w, const BatchLayout& 
     a.status_sys = reinterpret_cast<int*>(D(L.status_sys));
     a.stats_sys = reinterpret_cast<unsigned long long*>(D(L.stats_sys));
     a.B = B;
-    const void* fn = solve_kernel_ptr(G, true);
+    const void* fn = solve_kernel_ptr(G, true, true);
     Geometry geo;
     const int st = persistent_geometry(ctx, fn, 0, G, h.bucket_jn[q], &geo);
     if (st) return st;
@@ -746,7 +754,7 @@ int batch_enqueue(ibb_ctx* ctx, const BatchHost& h, char* w, const BatchLayout& 
 // *grow_f / *grow_o report a frontier or output overflow (the caller re-runs).
 int batch_finish(const BatchHost& h, char* w, const BatchLayout& L, long long ocap, hipStream_t s, double* out_lo,
                  double* out_hi, uint8_t* out_tag, int64_t cap, int64_t* out_off, int32_t* status, ibb_stats* stats,
-                 bool* grow_f, long long* grow_o) {
+                 bool* grow_f, long long* grow_o, long long* widest = nullptr) {
   const int B = h.B;
   auto D = [&](size_t off) { return w + off; };
   *grow_f = false;
@@ -758,9 +766,11 @@ int batch_finish(const BatchHost& h, char* w, const BatchLayout& L, long long oc
       hipStreamSynchronize(s) != hipSuccess)
     return IBB_ERR_DEVICE;
   for (int q = 0; q < 4; ++q) {
+    if (widest) widest[q] = 0;
     if (h.bucket_start[q + 1] == h.bucket_start[q]) continue;
     if (ctrls[q].status == IBB_ERR_QUEUE_OVERFLOW) *grow_f = true;
     else if (ctrls[q].status != 0) return ctrls[q].status;
+    if (widest) widest[q] = (long long)ctrls[q].max_frontier;
   }
   if (*grow_f) return IBB_OK;
   if ((long long)M > ocap) {
@@ -826,11 +836,31 @@ int batch_finish(const BatchHost& h, char* w, const BatchLayout& L, long long oc
 // of the member's node budget and the members' widest levels do not all
 // coincide, so a quarter of the summed budgets (each counted up to 2^20),
 // within [4 M, 64 M] boxes, or what an earlier batch on the context needed.
-long long batch_first_fcap(const ibb_ctx* ctx, int32_t B, const ibb_params* params, const int32_t* status) {
-  double sum = 0.0;
-  for (int b = 0; b < B; ++b)
-    if (status[b] == IBB_OK) sum += (double)std::min<int64_t>(params[b].max_boxes, 1LL << 20);
-  const long long f = std::min<long long>(1LL << 26, std::max<long long>(1LL << 22, (long long)(sum / 4.0)));
+// Frontier capacity (boxes) of a batch's first attempt.  When the autotuner has
+// measured every lane-count class present (ibb_batch_tune: the widest level
+// of a class's sample launch per member), the capacity is that width times
+// the members of each launch, with a margin of a half, for the widest launch;
+// otherwise a quarter of the members' node budgets (each at most 2^20).  At
+// least what an earlier batch on this context needed.
+long long batch_first_fcap(const ibb_ctx* ctx, int32_t B, const ibb_system* systems, const ibb_params* params,
+                           const int32_t* status, const ibb_batch_config* cfg) {
+  double sum = 0.0, launch[4] = {0, 0, 0, 0};
+  bool tuned = true;
+  for (int b = 0; b < B; ++b) {
+    if (status[b] != IBB_OK) continue;
+    sum += (double)std::min<int64_t>(params[b].max_boxes, 1LL << 20);
+    const int cls = lanes_class(lanes_for(systems[b].n));
+    const double w = ctx->batch_cfg[cls].front_per_member;
+    if (!(w > 0.0)) tuned = false;
+    launch[lanes_class(cfg[cls].lanes)] += w;
+  }
+  long long f;
+  if (tuned) {
+    const double widest = std::max(std::max(launch[0], launch[1]), std::max(launch[2], launch[3]));
+    f = std::min<long long>(1LL << 28, std::max<long long>(1LL << 16, (long long)(1.5 * widest)));
+  } else {
+    f = std::min<long long>(1LL << 26, std::max<long long>(1LL << 22, (long long)(sum / 4.0)));
+  }
   return std::max(f, ctx->batch_fcap);
 }
 
@@ -853,7 +883,7 @@ namespace {
 int solve_batch_with(ibb_ctx* ctx, const ibb_batch_config* cfg, int32_t B, const ibb_system* systems,
                      const double* lo, const double* hi, const ibb_params* params, double* out_lo, double* out_hi,
                      uint8_t* out_tag, int64_t cap, int64_t* out_off, int32_t* status, ibb_stats* stats,
-                     float* ms) {
+                     float* ms, long long* widest = nullptr) {
   if (hipSetDevice(ctx->device) != hipSuccess) return IBB_ERR_DEVICE;
   if (ms) *ms = 0.0f;
   BatchHost h;
@@ -864,7 +894,7 @@ int solve_batch_with(ibb_ctx* ctx, const ibb_batch_config* cfg, int32_t B, const
     return IBB_OK;
   }
   // capacities sized for the batch up front (an overflow re-runs the whole batch)
-  long long fcap = batch_first_fcap(ctx, B, params, status);
+  long long fcap = batch_first_fcap(ctx, B, systems, params, status, cfg);
   long long ocap = std::max<long long>(1LL << 15, 16LL * B);
   hipStream_t s = ctx->stream;
   for (int attempt = 0; attempt < 10; ++attempt) {
@@ -882,7 +912,8 @@ int solve_batch_with(ibb_ctx* ctx, const ibb_batch_config* cfg, int32_t B, const
     ctx->timed_pending = true;
     bool grow_f = false;
     long long grow_o = 0;
-    st = batch_finish(h, w, L, ocap, s, out_lo, out_hi, out_tag, cap, out_off, status, stats, &grow_f, &grow_o);
+    st = batch_finish(h, w, L, ocap, s, out_lo, out_hi, out_tag, cap, out_off, status, stats, &grow_f, &grow_o,
+                      widest);
     if (st) return st;
     if (grow_f) {
       fcap *= 4;
@@ -959,7 +990,7 @@ extern "C" int ibb_batch_tune(ibb_ctx* ctx, int32_t B, const ibb_system* systems
     const int G = 2 << q;
     // workgroups per CU that fit the natural launch
     Geometry geo;
-    int st = persistent_geometry(ctx, solve_kernel_ptr(G, true), 0, G, jn, &geo);
+    int st = persistent_geometry(ctx, solve_kernel_ptr(G, true, true), 0, G, jn, &geo);
     if (st) return st;
     const int full = geo.blocks / ctx->num_cu;
     const int part = std::max(1, (2 * full + 2) / 3);
@@ -984,6 +1015,7 @@ extern "C" int ibb_batch_tune(ibb_ctx* ctx, int32_t B, const ibb_system* systems
     std::vector<int32_t> stat((size_t)m), stat0((size_t)m);
     std::vector<ibb_stats> sts((size_t)m), sts0((size_t)m);
     std::vector<float> times(cands.size(), 0.0f);
+    double front_per_member = 0.0;
     for (size_t c = 0; c <= cands.size(); ++c) {
       // run 0 warms the default launch up; runs 1.. time the candidates
       const ibb_batch_config& cand = cands[c == 0 ? 0 : c - 1];
@@ -992,12 +1024,13 @@ extern "C" int ibb_batch_tune(ibb_ctx* ctx, int32_t B, const ibb_system* systems
       const int qe = lanes_class(cand.lanes);
       if (qe != q) cfg[qe] = ibb_batch_config{cand.lanes, cand.tiles_per_claim, cand.blocks_per_cu, 0, 0.0};
       float ms = 0.0f;
+      long long widest[4] = {0, 0, 0, 0};
       for (;;) {
         olo.assign((size_t)cap * kMaxN, 0.0);
         ohi.assign((size_t)cap * kMaxN, 0.0);
         otag.assign((size_t)cap, 0);
         st = solve_batch_with(ctx, cfg, m, ss.data(), ls.data(), hs.data(), ps.data(), olo.data(), ohi.data(),
-                              otag.data(), cap, off.data(), stat.data(), sts.data(), &ms);
+                              otag.data(), cap, off.data(), stat.data(), sts.data(), &ms, widest);
         if (st == IBB_ERR_OUTPUT_CAPACITY && off[(size_t)m] > cap) {
           cap = off[(size_t)m];
           continue;
@@ -1008,6 +1041,8 @@ extern "C" int ibb_batch_tune(ibb_ctx* ctx, int32_t B, const ibb_system* systems
       if (c == 0) {
         stat0 = stat;
         sts0 = sts;
+        // queue size: the widest level of the class's own launch, per member
+        front_per_member = (double)widest[q] / (double)m;
         continue;
       }
       // every configuration must reproduce the default's statuses and counters
@@ -1024,6 +1059,7 @@ extern "C" int ibb_batch_tune(ibb_ctx* ctx, int32_t B, const ibb_system* systems
     ibb_batch_config chosen = cands[best];
     chosen.tuned = 1;
     chosen.ms = (double)times[best];
+    chosen.front_per_member = std::max(front_per_member, 1.0);
     ctx->batch_cfg[q] = chosen;
   }
   return IBB_OK;
@@ -1100,7 +1136,7 @@ extern "C" int ibb_batch_plan_create(ibb_ctx* ctx, int32_t B, const ibb_system* 
     p->stream = nullptr;
     st = IBB_ERR_DEVICE;
   }
-  p->fcap = batch_first_fcap(ctx, B, params, p->status0.data());
+  p->fcap = batch_first_fcap(ctx, B, systems, params, p->status0.data(), ctx->batch_cfg);
   p->ocap = std::max<long long>(1LL << 15, 16LL * B);
   if (!st && p->h.any) st = plan_build(p);
   if (st) {
@@ -1179,6 +1215,8 @@ void ibb_params_default(ibb_params* p) {
   p->recontract_ratio = 0.5;
   p->hs_max_width = INFINITY;
   p->schedule = IBB_SCHEDULE_AUTO;
+  p->contractor = IBB_CONTRACT_HS;
+  p->inclusion = IBB_INCLUDE_NATURAL;
   p->reserved = 0;
 }
 
@@ -1528,10 +1566,15 @@ int ibb_selftest_ops(ibb_ctx* ctx, int32_t op, int64_t n, const double* a, const
 
 // ---------------------------------------------------------------------------
 // Serving: continuous batching.  Admitted solves occupy device slots; their
-// boxes share one frontier per size bucket; each scheduling round admits
-// queued requests that fit (a free slot and frontier boxes reserved for them),
-// runs a quantum of tree levels for every bucket, and harvests the solves that
-// ran out of boxes.  A solve's result does not depend on its neighbours.
+// boxes share one frontier per size bucket.  Each scheduling round (1) waits
+// for the device pass enqueued by the previous round and harvests the solves
+// that ran out of boxes, (2) admits queued requests whose reservation fits
+// the device pool and uploads them with one copy and one kernel, (3) makes
+// room for the next levels of every bucket (growing its frontier within the
+// pool, else failing the solves that outgrew their reservation the most) and
+// (4) enqueues the next pass of every bucket and returns, so that the host's
+// work of the next round overlaps the device's.  A solve's result does not
+// depend on its neighbours.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -1542,6 +1585,8 @@ struct Request {
   Compiled comp;
   double lo[kMaxN] = {0}, hi[kMaxN] = {0};
   ibb_params p{};
+  long long reserve_boxes = 0;  // frontier boxes reserved at admission
+  size_t reserve_bytes = 0;
   int slot = -1, bucket = -1;
   int state = 0;  // 0 queued, 1 on the device, 2 done
   int status = IBB_OK;
@@ -1558,13 +1603,38 @@ struct Bucket {
   uint32_t* meta[2] = {nullptr, nullptr};
   uint32_t* sys[2] = {nullptr, nullptr};
   void* mem = nullptr;
+  size_t bytes = 0;
   int level = 0;
   unsigned long long count = 0;  // boxes at `level`
-  long long reserved = 0;
-  std::vector<int> slots;  // active slots
+  std::vector<int> slots;        // active slots
 };
 
+// Device bytes of a bucket frontier of `cap` boxes of G lanes: two levels of
+// boxes, records and system indices.
+size_t bucket_bytes(int G, long long cap) { return (size_t)cap * 2 * (sizeof(double) * 2 * G + 8) + 4096; }
+
+// Frontier boxes reserved for a request: reserve_per_solve for every 64
+// bisections the tree needs at least (every coordinate halved from its width
+// down to tol), at most max_boxes + 1.
+long long reserve_for(const Request& r, long long per_solve) {
+  long long depth = 0;
+  for (int k = 0; k < r.comp.n; ++k) {
+    const double w = r.hi[k] - r.lo[k];
+    if (w > r.p.tol) depth += (long long)std::ceil(std::log2(w / r.p.tol));
+  }
+  const long long units = std::max<long long>(1, (depth + 63) / 64);
+  return std::min<long long>(r.p.max_boxes + 1, per_solve * units);
+}
+
 }  // namespace
+
+namespace ibb {
+hipError_t launch_admit(hipStream_t s, const AdmitRec* recs, int count, const uint64_t* payload, uint64_t* blobs,
+                        int slot_words, SysParams* sp, int* nsys, int* status_sys, uint8_t* evict,
+                        unsigned long long* stats_sys, unsigned long long* slot_count, unsigned long long* cum_sys,
+                        unsigned long long* pending, unsigned long long* count_sys, int S);
+hipError_t launch_evict(hipStream_t s, const int* slots, int count, uint8_t* evict, int* status_sys, int status);
+}  // namespace ibb
 
 struct ibb_server {
   ibb_ctx* ctx = nullptr;
@@ -1577,16 +1647,29 @@ struct ibb_server {
   unsigned long long *count_sys = nullptr, *cum_sys = nullptr, *stats_sys = nullptr, *slot_count = nullptr;
   unsigned long long* pending = nullptr;  // boxes of each slot still in a frontier
   int* status_sys = nullptr;
+  uint8_t* evict = nullptr;  // slots whose boxes the next pass drops
   double* out_box = nullptr;
   uint32_t* out_tag = nullptr;
   double *s_lo = nullptr, *s_hi = nullptr;
   uint8_t* s_tag = nullptr;
   long long* level_sizes = nullptr;
   Bucket bk[4];
+  size_t pool_used = 0;      // device bytes of the bucket frontiers
+  size_t reserved = 0;       // bytes reserved by the admitted solves
+  // per-round staging: admission records and compiled systems (host pinned,
+  // device), and the pinned mirror of the counters read back after a pass
+  char* h_stage = nullptr;
+  char* d_stage = nullptr;
+  size_t stage_bytes = 0;
+  char* h_back = nullptr;
+  size_t back_bytes = 0;
+  hipEvent_t pass_done = nullptr;
+  bool in_flight = false;
   std::deque<Request*> queue;
   std::map<int64_t, Request*> reqs;
   std::vector<Request*> by_slot;
   std::vector<int> free_slots;
+  std::vector<int64_t> finished;  // ids harvested and not yet reported
   int64_t next_id = 0;
 };
 
@@ -1610,6 +1693,7 @@ int alloc_bucket(Bucket& b, int G, long long cap) {
     b.mem = nullptr;
     return IBB_ERR_NO_MEMORY;
   }
+  b.bytes = o;
   char* w = static_cast<char*>(b.mem);
   b.ctrl = reinterpret_cast<Ctrl*>(w + c);
   b.front[0] = reinterpret_cast<double*>(w + f0);
@@ -1622,10 +1706,11 @@ int alloc_bucket(Bucket& b, int G, long long cap) {
   return IBB_OK;
 }
 
-// Moves a bucket to a larger frontier, keeping the boxes of its current level.
-int grow_bucket(Bucket& b, hipStream_t s) {
+// Moves a bucket to a frontier of new_cap boxes, keeping the boxes of its
+// current level.
+int grow_bucket(Bucket& b, long long new_cap, hipStream_t s) {
   Bucket nb;
-  int st = alloc_bucket(nb, b.G, b.cap * 4);
+  int st = alloc_bucket(nb, b.G, new_cap);
   if (st) return st;
   const int cur = b.level & 1;
   const size_t rec = sizeof(double) * 2 * b.G;
@@ -1638,10 +1723,113 @@ int grow_bucket(Bucket& b, hipStream_t s) {
   hipFree(b.mem);
   nb.level = b.level;
   nb.count = b.count;
-  nb.reserved = b.reserved;
   nb.slots = b.slots;
   b = nb;
   return IBB_OK;
+}
+
+int ensure_stage(ibb_server* sv, size_t need) {
+  if (sv->stage_bytes >= need) return IBB_OK;
+  need = std::max(need, sv->stage_bytes * 2);
+  if (sv->h_stage) hipHostFree(sv->h_stage);
+  if (sv->d_stage) hipFree(sv->d_stage);
+  sv->h_stage = sv->d_stage = nullptr;
+  sv->stage_bytes = 0;
+  if (hipHostMalloc(reinterpret_cast<void**>(&sv->h_stage), need, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&sv->d_stage), need) != hipSuccess)
+    return IBB_ERR_NO_MEMORY;
+  sv->stage_bytes = need;
+  return IBB_OK;
+}
+
+// Pinned mirror of what a pass brings back: the four control blocks, then
+// per slot the boxes still pending, the eight counters, the status, the
+// emitted boxes and the level counts.
+struct Back {
+  Ctrl* ctrls;
+  unsigned long long* pending;
+  unsigned long long* stats;
+  int* status;
+  unsigned long long* emitted;
+  unsigned long long* count_sys;
+};
+
+Back back_view(ibb_server* sv) {
+  const int S = sv->cfg.max_slots;
+  char* p = sv->h_back;
+  Back b;
+  b.ctrls = reinterpret_cast<Ctrl*>(p);
+  p += round_up(4 * sizeof(Ctrl), 256);
+  b.pending = reinterpret_cast<unsigned long long*>(p);
+  p += round_up(8ull * S, 256);
+  b.stats = reinterpret_cast<unsigned long long*>(p);
+  p += round_up(64ull * S, 256);
+  b.status = reinterpret_cast<int*>(p);
+  p += round_up(4ull * S, 256);
+  b.emitted = reinterpret_cast<unsigned long long*>(p);
+  p += round_up(8ull * S, 256);
+  b.count_sys = reinterpret_cast<unsigned long long*>(p);
+  return b;
+}
+
+size_t back_size(int S) {
+  return round_up(4 * sizeof(Ctrl), 256) + round_up(8ull * S, 256) + round_up(64ull * S, 256) +
+         round_up(4ull * S, 256) + round_up(8ull * S, 256) + round_up(24ull * S, 256);
+}
+
+// Harvest after a pass: bucket levels and counts, then every solve without
+// boxes left.  Returns the number harvested or a negative status.
+int harvest(ibb_server* sv) {
+  hipStream_t s = sv->ctx->stream;
+  const Back bk = back_view(sv);
+  for (int q = 0; q < 4; ++q) {
+    Bucket& b = sv->bk[q];
+    if (b.count == 0) continue;
+    if (bk.ctrls[q].status != 0) return bk.ctrls[q].status;
+    if ((int)bk.ctrls[q].levels > b.level) b.level = (int)bk.ctrls[q].levels;
+    b.count = bk.ctrls[q].count[b.level % 3];
+  }
+  int finished = 0;
+  for (int q = 0; q < 4; ++q) {
+    Bucket& b = sv->bk[q];
+    for (size_t i = 0; i < b.slots.size();) {
+      const int slot = b.slots[i];
+      if (bk.pending[slot] != 0) {
+        ++i;
+        continue;
+      }
+      Request* r = sv->by_slot[slot];
+      const int n = r->comp.n;
+      r->status = bk.status[slot];
+      int64_t* f = &r->stats.processed;
+      for (int k = 0; k < 8; ++k) f[k] = (int64_t)bk.stats[(size_t)slot * 8 + k];
+      const long long m = (long long)bk.emitted[slot];
+      if (r->status == IBB_OK && m > sv->cfg.out_cap_per_solve) r->status = IBB_ERR_OUTPUT_CAPACITY;
+      if (r->status == IBB_OK && m > 0) {
+        r->out_lo.resize((size_t)m * n);
+        r->out_hi.resize((size_t)m * n);
+        r->out_tag.resize((size_t)m);
+        if (launch_slot_sort(s, sv->out_box, sv->out_tag, sv->slot_count, slot, sv->cfg.out_cap_per_solve, n,
+                             sv->s_lo, sv->s_hi, sv->s_tag) != hipSuccess ||
+            hipMemcpyAsync(r->out_lo.data(), sv->s_lo, sizeof(double) * m * n, hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(r->out_hi.data(), sv->s_hi, sizeof(double) * m * n, hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(r->out_tag.data(), sv->s_tag, (size_t)m, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+          return IBB_ERR_DEVICE;
+      }
+      r->state = 2;
+      sv->by_slot[slot] = nullptr;
+      sv->free_slots.push_back(slot);
+      sv->reserved -= r->reserve_bytes;
+      sv->finished.push_back(r->id);
+      b.slots[i] = b.slots.back();
+      b.slots.pop_back();
+      ++finished;
+    }
+  }
+  return finished;
 }
 
 }  // namespace
@@ -1655,6 +1843,7 @@ void ibb_server_config_default(ibb_server_config* c) {
   c->reserve_per_solve = 1 << 14;
   c->levels_per_quantum = 8;
   c->out_cap_per_solve = 1024;
+  c->pool_bytes = 8ll << 30;
 }
 
 int ibb_server_create(ibb_ctx* ctx, const ibb_server_config* cfg, ibb_server** out) {
@@ -1666,6 +1855,9 @@ int ibb_server_create(ibb_ctx* ctx, const ibb_server_config* cfg, ibb_server** o
   if (c.max_slots < 1 || c.frontier_cap < 16 || c.reserve_per_solve < 1 || c.levels_per_quantum < 1 ||
       c.out_cap_per_solve < 1 || c.reserve_per_solve > c.frontier_cap)
     return IBB_ERR_INVALID_ARG;
+  size_t initial = 0;
+  for (int q = 0; q < 4; ++q) initial += bucket_bytes(2 << q, c.frontier_cap);
+  if (c.pool_bytes < (long long)initial) return IBB_ERR_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return IBB_ERR_DEVICE;
   ibb_server* sv = new (std::nothrow) ibb_server();
   if (!sv) return IBB_ERR_NO_MEMORY;
@@ -1684,7 +1876,8 @@ int ibb_server_create(ibb_ctx* ctx, const ibb_server_config* cfg, ibb_server** o
                a_st = take(8ull * 8 * S), a_sc = take(8ull * S), a_ss = take(4ull * S),
                a_ob = take(sizeof(double) * 2 * kMaxN * oc * S), a_ot = take(4ull * oc * S),
                a_slo = take(sizeof(double) * kMaxN * oc), a_shi = take(sizeof(double) * kMaxN * oc),
-               a_stag = take((size_t)oc), a_lv = take(sizeof(long long) * kLevelCap), a_pd = take(8ull * S);
+               a_stag = take((size_t)oc), a_lv = take(sizeof(long long) * kLevelCap), a_pd = take(8ull * S),
+               a_ev = take((size_t)S);
   if (hipMalloc(&sv->mem, o) != hipSuccess) {
     delete sv;
     return IBB_ERR_NO_MEMORY;
@@ -1706,13 +1899,21 @@ int ibb_server_create(ibb_ctx* ctx, const ibb_server_config* cfg, ibb_server** o
   sv->s_tag = reinterpret_cast<uint8_t*>(w + a_stag);
   sv->level_sizes = reinterpret_cast<long long*>(w + a_lv);
   sv->pending = reinterpret_cast<unsigned long long*>(w + a_pd);
+  sv->evict = reinterpret_cast<uint8_t*>(w + a_ev);
   std::vector<long long> boff((size_t)S);
   for (int i = 0; i < S; ++i) boff[i] = (long long)i * kSlotWords;
   int st = IBB_OK;
   if (hipMemset(sv->mem, 0, o) != hipSuccess ||
-      hipMemcpy(sv->boff, boff.data(), 8ull * S, hipMemcpyHostToDevice) != hipSuccess)
+      hipMemcpy(sv->boff, boff.data(), 8ull * S, hipMemcpyHostToDevice) != hipSuccess ||
+      hipEventCreateWithFlags(&sv->pass_done, hipEventDisableTiming) != hipSuccess)
     st = IBB_ERR_DEVICE;
-  for (int q = 0; q < 4 && !st; ++q) st = alloc_bucket(sv->bk[q], 2 << q, c.frontier_cap);
+  sv->back_bytes = back_size(S);
+  if (!st && hipHostMalloc(reinterpret_cast<void**>(&sv->h_back), sv->back_bytes, hipHostMallocDefault) != hipSuccess)
+    st = IBB_ERR_NO_MEMORY;
+  for (int q = 0; q < 4 && !st; ++q) {
+    st = alloc_bucket(sv->bk[q], 2 << q, c.frontier_cap);
+    sv->pool_used += sv->bk[q].bytes;
+  }
   if (st) {
     ibb_server_destroy(sv);
     return st;
@@ -1730,6 +1931,10 @@ void ibb_server_destroy(ibb_server* sv) {
   for (auto& b : sv->bk)
     if (b.mem) hipFree(b.mem);
   if (sv->mem) hipFree(sv->mem);
+  if (sv->d_stage) hipFree(sv->d_stage);
+  if (sv->h_stage) hipHostFree(sv->h_stage);
+  if (sv->h_back) hipHostFree(sv->h_back);
+  if (sv->pass_done) hipEventDestroy(sv->pass_done);
   for (auto& kv : sv->reqs) delete kv.second;
   delete sv;
 }
@@ -1756,6 +1961,9 @@ int64_t ibb_server_submit(ibb_server* sv, const ibb_system* sys, const double* l
   std::memcpy(r->lo, lo, sizeof(double) * sys->n);
   std::memcpy(r->hi, hi, sizeof(double) * sys->n);
   r->p = *params;
+  r->reserve_boxes = reserve_for(*r, sv->cfg.reserve_per_solve);
+  r->reserve_bytes = bucket_bytes(r->comp.G, 2 * r->reserve_boxes) - 4096;
+  if ((long long)r->reserve_bytes > sv->cfg.pool_bytes) r->reserve_bytes = (size_t)sv->cfg.pool_bytes;
   sv->queue.push_back(r);
   sv->reqs[r->id] = r;
   return r->id;
@@ -1780,18 +1988,34 @@ int ibb_server_pending(ibb_server* sv, int64_t* queued, int64_t* active) {
   return IBB_OK;
 }
 
+int64_t ibb_server_finished(ibb_server* sv, int64_t* ids, int64_t cap) {
+  if (!sv || cap < 0 || (cap > 0 && !ids)) return IBB_ERR_INVALID_ARG;
+  const int64_t m = std::min<int64_t>(cap, (int64_t)sv->finished.size());
+  std::copy(sv->finished.begin(), sv->finished.begin() + m, ids);
+  sv->finished.erase(sv->finished.begin(), sv->finished.begin() + m);
+  return m;
+}
+
 int ibb_server_step(ibb_server* sv) {
   if (!sv) return IBB_ERR_INVALID_ARG;
   ibb_ctx* ctx = sv->ctx;
   if (hipSetDevice(ctx->device) != hipSuccess) return IBB_ERR_DEVICE;
   hipStream_t s = ctx->stream;
   const int S = sv->cfg.max_slots;
-  // ---- admission: a free slot and the frontier boxes the solve reserves
+  // ---- (1) the pass in flight: wait for it, harvest
+  int finished = 0;
+  if (sv->in_flight) {
+    if (hipEventSynchronize(sv->pass_done) != hipSuccess) return IBB_ERR_DEVICE;
+    sv->in_flight = false;
+    finished = harvest(sv);
+    if (finished < 0) return finished;
+  }
+  const Back bk = back_view(sv);
+  // ---- (2) admission: a free slot and the request's reservation within the pool
   std::vector<Request*> admitted;
   for (auto it = sv->queue.begin(); it != sv->queue.end() && !sv->free_slots.empty();) {
     Request* r = *it;
-    Bucket& b = sv->bk[bucket_of(r->comp.G)];
-    if (b.reserved + sv->cfg.reserve_per_solve > b.cap) {
+    if (sv->reserved + r->reserve_bytes > (size_t)sv->cfg.pool_bytes) {
       ++it;
       continue;
     }
@@ -1800,52 +2024,117 @@ int ibb_server_step(ibb_server* sv) {
     sv->free_slots.pop_back();
     r->bucket = bucket_of(r->comp.G);
     r->state = 1;
-    b.reserved += sv->cfg.reserve_per_solve;
-    b.slots.push_back(r->slot);
+    sv->reserved += r->reserve_bytes;
+    sv->bk[r->bucket].slots.push_back(r->slot);
     sv->by_slot[r->slot] = r;
     admitted.push_back(r);
   }
-  for (Request* r : admitted) {
-    Bucket& b = sv->bk[r->bucket];
-    const int slot = r->slot, L = b.level, G = b.G, n = r->comp.n;
-    // table, parameters and level bookkeeping of the slot; the root box joins
-    // the bucket's frontier at its current level
-    const SysParams spv{r->p.tol, r->p.recontract_ratio, r->p.hs_max_width, r->p.max_boxes, r->p.split_mode,
-                        r->p.max_recontract};
-    unsigned long long cs[3] = {0, 0, 0};
-    cs[L % 3] = 1;
-    std::vector<double> rec((size_t)2 * G, 0.0);
-    for (int k = 0; k < n; ++k) {
-      rec[2 * k] = r->lo[k];
-      rec[2 * k + 1] = -r->hi[k];
+  // room for the admitted roots (one box each) in their buckets' levels
+  long long add[4] = {0, 0, 0, 0};
+  for (Request* r : admitted) ++add[r->bucket];
+  // ---- (3) room for the next levels: grow within the pool, else fail the
+  // solves that outgrew their reservation the most (their boxes are dropped
+  // when the next pass loads them; they end with IBB_ERR_QUEUE_OVERFLOW)
+  std::vector<int> evicted;
+  long long live[4];
+  for (int q = 0; q < 4; ++q) {
+    Bucket& b = sv->bk[q];
+    const unsigned long long cur = b.count + (unsigned long long)add[q];
+    live[q] = (long long)cur;
+    if (cur == 0) continue;
+    if ((long long)cur * 2 <= b.cap && b.cap >= (long long)cur) continue;
+    const long long want = std::max<long long>(b.cap * 4, (long long)cur * 2);
+    long long fit = want;
+    const size_t others = sv->pool_used - b.bytes;
+    while (fit > b.cap && others + bucket_bytes(b.G, fit) > (size_t)sv->cfg.pool_bytes) fit = fit * 3 / 4;
+    if (fit >= (long long)cur * 2 && fit > b.cap) {
+      const int st = grow_bucket(b, fit, s);
+      if (st) return st;
+      sv->pool_used = others + b.bytes;
+      continue;
     }
-    const uint32_t zero = 0, sid = (uint32_t)slot;
-    const unsigned long long z8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const int zi = 0;
-    const unsigned long long newc = b.count + 1;
-    bool ok = hipMemcpy(sv->blobs + (size_t)slot * kSlotWords, r->comp.blob.data(), 8 * r->comp.blob.size(),
-                        hipMemcpyHostToDevice) == hipSuccess &&
-              hipMemcpy(sv->sp + slot, &spv, sizeof spv, hipMemcpyHostToDevice) == hipSuccess &&
-              hipMemcpy(sv->nsys + slot, &n, sizeof n, hipMemcpyHostToDevice) == hipSuccess &&
-              hipMemcpy(sv->status_sys + slot, &zi, sizeof zi, hipMemcpyHostToDevice) == hipSuccess &&
-              hipMemcpy(sv->stats_sys + (size_t)slot * 8, z8, sizeof z8, hipMemcpyHostToDevice) == hipSuccess &&
-              hipMemcpy(sv->slot_count + slot, z8, 8, hipMemcpyHostToDevice) == hipSuccess &&
-              hipMemcpy(sv->cum_sys + slot, z8, 8, hipMemcpyHostToDevice) == hipSuccess &&
-              hipMemcpy(sv->cum_sys + S + slot, z8, 8, hipMemcpyHostToDevice) == hipSuccess &&
-              hipMemcpy(sv->pending + slot, &cs[L % 3], 8, hipMemcpyHostToDevice) == hipSuccess;
-    for (int q = 0; q < 3 && ok; ++q)
-      ok = hipMemcpy(sv->count_sys + (size_t)q * S + slot, &cs[q], 8, hipMemcpyHostToDevice) == hipSuccess;
-    ok = ok &&
-         hipMemcpy(b.front[L & 1] + (size_t)b.count * 2 * G, rec.data(), sizeof(double) * 2 * G,
-                   hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(b.meta[L & 1] + b.count, &zero, 4, hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(b.sys[L & 1] + b.count, &sid, 4, hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(&b.ctrl->count[L % 3], &newc, 8, hipMemcpyHostToDevice) == hipSuccess;
-    if (!ok) return IBB_ERR_DEVICE;
-    b.count = newc;
+    // evict: boxes of this level per slot beyond the slot's reservation
+    std::vector<std::pair<long long, int>> over;
+    for (int slot : b.slots) {
+      const Request* r = sv->by_slot[slot];
+      const long long c = r->state == 1 && std::find(admitted.begin(), admitted.end(), r) == admitted.end()
+                              ? (long long)bk.count_sys[(size_t)(b.level % 3) * S + slot]
+                              : 1;
+      over.push_back({c - r->reserve_boxes, slot});
+    }
+    std::sort(over.begin(), over.end(), [](auto& x, auto& y) { return x.first > y.first; });
+    for (const auto& e : over) {
+      if (live[q] * 2 <= b.cap) break;
+      const long long c = e.first + sv->by_slot[e.second]->reserve_boxes;
+      evicted.push_back(e.second);
+      live[q] -= c;
+    }
   }
-  if (!admitted.empty() && launch_prep(s, sv->blobs, sv->boff, S) != hipSuccess) return IBB_ERR_DEVICE;
-  // ---- one quantum of levels per bucket
+  // ---- upload: admission records, compiled systems, evicted slots
+  size_t words = 0;
+  for (Request* r : admitted) words += r->comp.blob.size();
+  const size_t recs_at = 0, payload_at = round_up(sizeof(AdmitRec) * admitted.size(), 256),
+               evict_at = payload_at + round_up(8 * words, 256), boff_at = evict_at + round_up(4 * evicted.size(), 256),
+               need = boff_at + round_up(8 * admitted.size(), 256) + 256;
+  if (!admitted.empty() || !evicted.empty()) {
+    int st = ensure_stage(sv, need);
+    if (st) return st;
+    AdmitRec* recs = reinterpret_cast<AdmitRec*>(sv->h_stage + recs_at);
+    uint64_t* payload = reinterpret_cast<uint64_t*>(sv->h_stage + payload_at);
+    long long* boff = reinterpret_cast<long long*>(sv->h_stage + boff_at);
+    size_t w = 0;
+    for (size_t k = 0; k < admitted.size(); ++k) {
+      Request* r = admitted[k];
+      Bucket& b = sv->bk[r->bucket];
+      AdmitRec& a = recs[k];
+      std::memset(&a, 0, sizeof a);
+      a.slot = r->slot;
+      a.n = r->comp.n;
+      a.G = b.G;
+      a.nwords = (int32_t)r->comp.blob.size();
+      a.blob_at = (long long)w;
+      std::memcpy(payload + w, r->comp.blob.data(), 8 * r->comp.blob.size());
+      w += r->comp.blob.size();
+      a.sp = SysParams{r->p.tol, r->p.recontract_ratio, r->p.hs_max_width, r->p.max_boxes, r->p.split_mode,
+                       r->p.max_recontract, r->p.contractor, r->p.inclusion};
+      const int L = b.level;
+      a.front = b.front[L & 1];
+      a.meta = b.meta[L & 1];
+      a.sys = b.sys[L & 1];
+      a.pos = (long long)b.count;
+      b.count += 1;
+      a.ctrl = b.ctrl;
+      a.new_count = b.count;
+      a.level_slot = L % 3;
+      for (int i = 0; i < r->comp.n; ++i) {
+        a.lo[i] = r->lo[i];
+        a.hi[i] = r->hi[i];
+      }
+      boff[k] = (long long)r->slot * kSlotWords;
+    }
+    // the last admission of each bucket sets the bucket's level count
+    for (size_t k = admitted.size(); k-- > 0;) {
+      bool later = false;
+      for (size_t j = k + 1; j < admitted.size(); ++j) later = later || admitted[j]->bucket == admitted[k]->bucket;
+      recs[k].set_count = later ? 0 : 1;
+    }
+    int* ev = reinterpret_cast<int*>(sv->h_stage + evict_at);
+    for (size_t k = 0; k < evicted.size(); ++k) ev[k] = evicted[k];
+    if (hipMemcpyAsync(sv->d_stage, sv->h_stage, need, hipMemcpyHostToDevice, s) != hipSuccess) return IBB_ERR_DEVICE;
+    if (!admitted.empty()) {
+      if (launch_admit(s, reinterpret_cast<const AdmitRec*>(sv->d_stage + recs_at), (int)admitted.size(),
+                       reinterpret_cast<const uint64_t*>(sv->d_stage + payload_at), sv->blobs, kSlotWords, sv->sp,
+                       sv->nsys, sv->status_sys, sv->evict, sv->stats_sys, sv->slot_count, sv->cum_sys,
+                       sv->pending, sv->count_sys, S) != hipSuccess ||
+          launch_prep(s, sv->blobs, reinterpret_cast<const long long*>(sv->d_stage + boff_at), (int)admitted.size()) !=
+              hipSuccess)
+        return IBB_ERR_DEVICE;
+    }
+    if (!evicted.empty() && launch_evict(s, reinterpret_cast<const int*>(sv->d_stage + evict_at), (int)evicted.size(),
+                                         sv->evict, sv->status_sys, IBB_ERR_QUEUE_OVERFLOW) != hipSuccess)
+      return IBB_ERR_DEVICE;
+  }
+  // ---- (4) one pass of levels per bucket, then the counters back to the host
   bool any = false;
   ctx->tune_pending = false;
   hipEventRecord(ctx->ev0, s);
@@ -1853,16 +2142,10 @@ int ibb_server_step(ibb_server* sv) {
     Bucket& b = sv->bk[q];
     if (b.count == 0) continue;
     // at most two children per box per level (widest split): keep the frontier
-    // within capacity for the whole quantum
+    // within capacity for the whole pass
     int K = sv->cfg.levels_per_quantum;
-    while (K > 1 && (double)b.count * (double)(1ull << K) > (double)b.cap) --K;
-    while ((double)b.count * 2.0 > (double)b.cap) {
-      const int st = grow_bucket(b, s);
-      if (st) return st;
-    }
-    const unsigned long long zero_bar = 0;
-    if (hipMemcpy(&b.ctrl->bar, &zero_bar, sizeof zero_bar, hipMemcpyHostToDevice) != hipSuccess)
-      return IBB_ERR_DEVICE;
+    const double lv = (double)std::max<long long>(live[q], 1);
+    while (K > 1 && lv * (double)(1ull << K) > (double)b.cap) --K;
     SolveArgs a;
     std::memset(&a, 0, sizeof a);
     a.front[0] = b.front[0];
@@ -1892,17 +2175,20 @@ int ibb_server_step(ibb_server* sv) {
     a.status_sys = sv->status_sys;
     a.stats_sys = sv->stats_sys;
     a.pending_sys = sv->pending;
+    a.evict = sv->evict;
     a.B = S;
     // the Jacobian scratch fits the largest system of the bucket's active slots
     int jn = 0;
     for (int slot : b.slots) jn = std::max(jn, sv->by_slot[slot]->comp.n);
-    const void* fn = solve_kernel_ptr(b.G, true);
+    const void* fn = solve_kernel_ptr(b.G, true, true);
     Geometry geo;
     const int st = persistent_geometry(ctx, fn, 0, b.G, jn, &geo);
     if (st) return st;
     a.nblocks = geo.blocks;
     a.jrs = geo.jrs;
     a.jn = jn;
+    // the grid barrier counts arrivals from zero in every pass
+    if (launch_fill_u64(s, &b.ctrl->bar, 1, 0ull) != hipSuccess) return IBB_ERR_DEVICE;
     void* args[] = {&a};
     if (hipLaunchCooperativeKernel(fn, dim3(geo.blocks), dim3(64 * geo.waves), args, (unsigned)geo.lds, s) !=
         hipSuccess)
@@ -1911,67 +2197,19 @@ int ibb_server_step(ibb_server* sv) {
   }
   hipEventRecord(ctx->ev1, s);
   ctx->timed_pending = any;
-  // ---- bring back the control blocks and the per-slot counters
-  Ctrl ctrls[4];
-  std::vector<unsigned long long> cs((size_t)S), st8((size_t)8 * S);
-  std::vector<int> sst((size_t)S);
-  if (hipMemcpyAsync(&ctrls[0], sv->bk[0].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(&ctrls[1], sv->bk[1].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(&ctrls[2], sv->bk[2].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(&ctrls[3], sv->bk[3].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(cs.data(), sv->pending, 8ull * S, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(st8.data(), sv->stats_sys, 8ull * 8 * S, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(sst.data(), sv->status_sys, 4ull * S, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return IBB_ERR_DEVICE;
-  for (int q = 0; q < 4; ++q) {
-    Bucket& b = sv->bk[q];
-    if (b.count == 0) continue;
-    if (ctrls[q].status != 0) return ctrls[q].status;
-    if ((int)ctrls[q].levels > b.level) b.level = (int)ctrls[q].levels;
-    b.count = ctrls[q].count[b.level % 3];
-  }
-  // ---- harvest the solves without boxes left
-  int finished = 0;
-  std::vector<unsigned long long> emitted((size_t)S);
-  if (hipMemcpy(emitted.data(), sv->slot_count, 8ull * S, hipMemcpyDeviceToHost) != hipSuccess) return IBB_ERR_DEVICE;
-  for (int q = 0; q < 4; ++q) {
-    Bucket& b = sv->bk[q];
-    for (size_t i = 0; i < b.slots.size();) {
-      const int slot = b.slots[i];
-      if (cs[(size_t)slot] != 0) {
-        ++i;
-        continue;
-      }
-      Request* r = sv->by_slot[slot];
-      const int n = r->comp.n;
-      r->status = sst[slot];
-      int64_t* f = &r->stats.processed;
-      for (int k = 0; k < 8; ++k) f[k] = (int64_t)st8[(size_t)slot * 8 + k];
-      const long long m = (long long)emitted[slot];
-      if (r->status == IBB_OK && m > sv->cfg.out_cap_per_solve) r->status = IBB_ERR_OUTPUT_CAPACITY;
-      if (r->status == IBB_OK && m > 0) {
-        r->out_lo.resize((size_t)m * n);
-        r->out_hi.resize((size_t)m * n);
-        r->out_tag.resize((size_t)m);
-        if (launch_slot_sort(s, sv->out_box, sv->out_tag, sv->slot_count, slot, sv->cfg.out_cap_per_solve, n,
-                             sv->s_lo, sv->s_hi, sv->s_tag) != hipSuccess ||
-            hipMemcpyAsync(r->out_lo.data(), sv->s_lo, sizeof(double) * m * n, hipMemcpyDeviceToHost, s) !=
-                hipSuccess ||
-            hipMemcpyAsync(r->out_hi.data(), sv->s_hi, sizeof(double) * m * n, hipMemcpyDeviceToHost, s) !=
-                hipSuccess ||
-            hipMemcpyAsync(r->out_tag.data(), sv->s_tag, (size_t)m, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-          return IBB_ERR_DEVICE;
-      }
-      r->state = 2;
-      sv->by_slot[slot] = nullptr;
-      sv->free_slots.push_back(slot);
-      b.reserved -= sv->cfg.reserve_per_solve;
-      b.slots[i] = b.slots.back();
-      b.slots.pop_back();
-      ++finished;
-    }
+  if (any) {
+    const Back back = back_view(sv);
+    for (int q = 0; q < 4; ++q)
+      if (hipMemcpyAsync(&back.ctrls[q], sv->bk[q].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return IBB_ERR_DEVICE;
+    if (hipMemcpyAsync(back.pending, sv->pending, 8ull * S, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(back.stats, sv->stats_sys, 64ull * S, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(back.status, sv->status_sys, 4ull * S, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(back.emitted, sv->slot_count, 8ull * S, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(back.count_sys, sv->count_sys, 24ull * S, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipEventRecord(sv->pass_done, s) != hipSuccess)
+      return IBB_ERR_DEVICE;
+    sv->in_flight = true;
   }
   return finished;
 }

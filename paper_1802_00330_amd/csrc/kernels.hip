@@ -208,8 +208,11 @@ struct Scratch {
   iv Fc[W][G + 1];     // F at the expansion point
   iv Xc[W][G + 1];     // expansion point as degenerate intervals
   float row[W][G + 1]; // broadcast buffer of the single-precision solver
-  unsigned long long cnt[8];  // the wave's tree counters
 };
+
+// A wave's LDS region: its eight tree counters (64 bytes), then Scratch<G>,
+// then the Jacobian of its W boxes.
+constexpr size_t kWaveHeader = 64;
 
 // The interval Jacobian of the W boxes follows the Scratch block: box g, row
 // r, column k at g * (jn * rs + 1) + r * rs + k, with jn = n for one system
@@ -220,8 +223,10 @@ struct Scratch {
 // it when it would cost resident waves).
 template <int G>
 __host__ __device__ constexpr size_t wave_scratch_bytes(int jn, int rs) {
-  return ((sizeof(Scratch<G>) + 15) / 16) * 16 + (size_t)(64 / G) * (jn * rs + 1) * sizeof(iv);
+  return kWaveHeader + ((sizeof(Scratch<G>) + 15) / 16) * 16 + (size_t)(64 / G) * (jn * rs + 1) * sizeof(iv);
 }
+
+
 
 struct JView {
   iv* p;
@@ -417,8 +422,11 @@ struct Stage {
 // group's box is in ring slot qslot (valid when qvalid), children are
 // reserved at the ring's tail and published through qseq.  STAGED: the
 // boxes are the next (at most W) records of the wave's staging ring, which
-// passed the exclusion test and were counted when they were screened.
-template <int G, bool MULTI, bool QUEUE = false, bool STAGED = false>
+// passed the exclusion test and were counted when they were screened.  VAR:
+// the step also supports the Krawczyk contractor and the mean-value test
+// (chosen per system at run time); without it, only Hansen-Sengupta and the
+// natural extension are compiled in.
+template <int G, bool MULTI, bool QUEUE = false, bool STAGED = false, bool VAR = true>
 __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, Scratch<G>& S, const JView J,
                           long long base,
                           long long cnt, int cur, int level, unsigned long long* next_count,
@@ -433,18 +441,19 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
   // the group's system: its table, size and parameters
   LTable T = Tl;
   uint32_t sysid = 0;
-  double p_tol = a.tol, p_ratio = a.ratio, p_hsw = a.hs_max_width;
-  int p_split = a.split_mode, p_maxrc = a.max_rc;
+  double p_hsw = a.hs_max_width;
+  // split mode (bits 0-1), contractor (bit 2), inclusion (bit 3), most
+  // consecutive re-contractions (bits 8-15): one register per group in batches
+  int p_mode = a.split_mode | (a.contractor << 2) | (a.inclusion << 3) | (a.max_rc << 8);
   unsigned long long room = 0;  // batches: nodes the system may add at the next level
   if (MULTI) {
     if (valid) sysid = a.sys[cur][idx];
+    // serving: a system the host failed (its boxes outgrew the device pool)
+    if (valid && a.evict && a.evict[sysid]) valid = false;
     T = global_table(a.blobs + a.blob_off[sysid]);
     const SysParams sp = a.sp[sysid];
-    p_tol = sp.tol;
-    p_ratio = sp.ratio;
     p_hsw = sp.hs_max_width;
-    p_split = sp.split_mode;
-    p_maxrc = sp.max_rc;
+    p_mode = sp.split_mode | (sp.contractor << 2) | (sp.inclusion << 3) | (sp.max_rc << 8);
     if (valid) {
       // the budget is on the system's tree nodes, checked level by level
       const unsigned long long total =
@@ -501,12 +510,16 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
 
   // ---- width of X
   const double w = group_max<G>((active && row_ok) ? iwidth(S.X[g][r]) : 0.0);
-  const bool do_hs = active && !(w > p_hsw);
+  bool do_hs = active && !(w > p_hsw);
+  // the mean-value form (a centred inclusion of F) as a second exclusion
+  // test, on boxes not proven to hold a root
+  const bool do_mv = VAR && active && !proven && ((p_mode >> 3) & 1) != 0;
+  const bool do_j = do_hs || do_mv;
 
-  bool hs_empty = false, hs_unique = false, run = false;
-  if (__ballot(do_hs) != 0) {
+  bool hs_empty = false, hs_unique = false, run = false, mv_excl = false;
+  if (__ballot(do_j) != 0) {
     // H1, H8: expansion point x = mid X and X - x
-    if (do_hs && row_ok) {
+    if (do_j && row_ok) {
       const iv x = S.X[g][r];
       const double m = imid(x);
       S.Xc[g][r] = point_iv(m);
@@ -514,7 +527,7 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
     }
     wave_lds_sync();
     // H2, H3: row r of J(X); F_r at the degenerate box [x, x]
-    if (do_hs && row_ok) {
+    if (do_j && row_ok) {
       for (int k = 0; k < n; ++k) J(g, r, k) = eval_partial(T, r, k, S.X[g]);
       S.Fc[g][r] = eval_equation(T, r, S.Xc[g]);
       if (dbg) {
@@ -527,6 +540,18 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
       }
     }
     wave_lds_sync();
+    // mean-value form: F_r(x) + sum_k J_rk(X) (X_k - x_k), k ascending; the box
+    // is discarded when some row excludes 0 (its natural F(X) held 0)
+    if (VAR && __ballot(do_mv) != 0) {
+      bool ex_row = false;
+      if (do_mv && row_ok) {
+        iv acc = S.Fc[g][r];
+        for (int k = 0; k < n; ++k) acc = iadd(acc, imul(J(g, r, k), S.D[g][k]));
+        ex_row = acc.lo > 0.0 || acc.nhi > 0.0;
+      }
+      mv_excl = do_mv && group_bits<G>(__ballot(ex_row), g) != 0;
+      do_hs = do_hs && !mv_excl;
+    }
     // H4: single-precision mid J, row r
     float M[G];
 #pragma unroll
@@ -691,50 +716,78 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
         dbg[dbg_off_P(n) + (pos * n + j) * 2 + 1] = -J(g, pos, j).nhi;
       }
     }
-    // S_U = sum_{j > pos} P[pos][j] (X_j - x_j), j ascending
-    iv SU{0.0, 0.0};
-    bool hasU = false;
-    if (run && row_ok) {
-      for (int j = pos + 1; j < n; ++j) {
-        const iv t = imul(J(g, pos, j), S.D[g][j]);
-        SU = hasU ? iadd(SU, t) : t;
-        hasU = true;
-      }
-    }
-
-    // H9: Gauss-Seidel sweep (eq 21-22).  The bracket
-    //   g_i + sum_{j<i} P_ij (X'_j - x_j) + sum_{j>i} P_ij (X_j - x_j)
-    // is formed as (g_i + S_L) + S_U, each sum on its own, j ascending.
-    iv SL{0.0, 0.0};
-    bool hasL = false;
     bool my_unique = true, my_empty = false;
-    const int nsweep = MULTI ? G : n;
-    for (int i = 0; i < nsweep; ++i) {
-      if (run && row_ok && pos == i) {
-        iv N = gv;
-        if (hasL) N = iadd(N, SL);
-        if (hasU) N = iadd(N, SU);
-        const double xc = S.Xc[g][i].lo;
-        iv xn;
-        bool inside = false;
-        const bool ok = gs_component(N, J(g, i, i), xc, S.X[g][i], xn, inside);
-        my_empty = !ok;
-        my_unique = ok && inside;
-        if (!ok) xn = S.X[g][i];
-        if (dbg) {
-          dbg[dbg_off_N(n) + 2 * i] = N.lo;
-          dbg[dbg_off_N(n) + 2 * i + 1] = -N.nhi;
-          dbg[dbg_off_X(n) + 2 * i] = xn.lo;
-          dbg[dbg_off_X(n) + 2 * i + 1] = -xn.nhi;
+    if (VAR && ((p_mode >> 2) & 1)) {
+      // Krawczyk (eq 15-16): K = x - g + (I - P)(X - x), every component
+      // from X; X' = K meets X; K inside the interior of X proves one root.
+      // The sum over j ascending starts from its first term.
+      if (run && row_ok) {
+        iv SK{0.0, 0.0};
+        for (int j = 0; j < n; ++j) {
+          const iv pj = J(g, pos, j);
+          const iv m = (j == pos) ? isub(point_iv(1.0), pj) : iv{pj.nhi, pj.lo};  // 1 - P_jj or -P_ij
+          const iv t = imul(m, S.D[g][j]);
+          SK = j ? iadd(SK, t) : t;
         }
-        S.Xn[g][i] = xn;
-        S.D[g][i] = isub(xn, point_iv(xc));
+        const double xc = S.Xc[g][pos].lo;
+        const iv K = iadd(isub(point_iv(xc), gv), SK);
+        const iv Xi = S.X[g][pos];
+        const double il = fmax(K.lo, Xi.lo), inh = fmax(K.nhi, Xi.nhi);
+        my_empty = il > -inh;
+        my_unique = !my_empty && Xi.lo < K.lo && Xi.nhi < K.nhi;
+        const iv xn = my_empty ? Xi : iv{il, inh};
+        if (dbg) {
+          dbg[dbg_off_N(n) + 2 * pos] = K.lo;
+          dbg[dbg_off_N(n) + 2 * pos + 1] = -K.nhi;
+          dbg[dbg_off_X(n) + 2 * pos] = xn.lo;
+          dbg[dbg_off_X(n) + 2 * pos + 1] = -xn.nhi;
+        }
+        S.Xn[g][pos] = xn;
       }
       wave_lds_sync();
-      if (run && row_ok && pos > i) {
-        const iv t = imul(J(g, pos, i), S.D[g][i]);
-        SL = hasL ? iadd(SL, t) : t;
-        hasL = true;
+    } else {
+      // H9: Gauss-Seidel sweep (eq 21-22).  The bracket
+      //   g_i + sum_{j<i} P_ij (X'_j - x_j) + sum_{j>i} P_ij (X_j - x_j)
+      // is formed as (g_i + S_L) + S_U, each sum on its own, j ascending.
+      iv SU{0.0, 0.0};
+      bool hasU = false;
+      if (run && row_ok) {
+        for (int j = pos + 1; j < n; ++j) {
+          const iv t = imul(J(g, pos, j), S.D[g][j]);
+          SU = hasU ? iadd(SU, t) : t;
+          hasU = true;
+        }
+      }
+      iv SL{0.0, 0.0};
+      bool hasL = false;
+      const int nsweep = MULTI ? G : n;
+      for (int i = 0; i < nsweep; ++i) {
+        if (run && row_ok && pos == i) {
+          iv N = gv;
+          if (hasL) N = iadd(N, SL);
+          if (hasU) N = iadd(N, SU);
+          const double xc = S.Xc[g][i].lo;
+          iv xn;
+          bool inside = false;
+          const bool ok = gs_component(N, J(g, i, i), xc, S.X[g][i], xn, inside);
+          my_empty = !ok;
+          my_unique = ok && inside;
+          if (!ok) xn = S.X[g][i];
+          if (dbg) {
+            dbg[dbg_off_N(n) + 2 * i] = N.lo;
+            dbg[dbg_off_N(n) + 2 * i + 1] = -N.nhi;
+            dbg[dbg_off_X(n) + 2 * i] = xn.lo;
+            dbg[dbg_off_X(n) + 2 * i + 1] = -xn.nhi;
+          }
+          S.Xn[g][i] = xn;
+          S.D[g][i] = isub(xn, point_iv(xc));
+        }
+        wave_lds_sync();
+        if (run && row_ok && pos > i) {
+          const iv t = imul(J(g, pos, i), S.D[g][i]);
+          SL = hasL ? iadd(SL, t) : t;
+          hasL = true;
+        }
       }
     }
     hs_empty = run && group_bits<G>(__ballot(my_empty), g) != 0;
@@ -750,7 +803,7 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
   wave_lds_sync();
 
   // ---- decisions (S3-S7), uniform per group
-  const bool alive = active && !hs_empty;
+  const bool alive = active && !mv_excl && !hs_empty;
   const bool prv = proven || (alive && run && hs_unique);
   double wn = (alive && row_ok) ? iwidth(S.Xn[g][r]) : -1.0;
   int kk = r, whok = r;
@@ -764,12 +817,16 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
   uint32_t child_meta = 0;
   double mid_kk = 0.0;
   uint32_t split_mask = 0;
+  // tolerance and re-contraction ratio, read where they are used (batches:
+  // the group's system; fewer values live across the contraction)
+  const double p_tol = MULTI ? a.sp[sysid].tol : a.tol;
+  const double p_ratio = MULTI ? a.sp[sysid].ratio : a.ratio;
   if (alive) {
     if (wn <= p_tol) {
       emit = true;
       tag = prv ? 1 : 0;
     } else if (prv) {
-      if (wn < w && rc + 1 < p_maxrc) {
+      if (wn < w && rc + 1 < (p_mode >> 8)) {
         kind = 1;
         n_push = 1;
         child_meta = 1u | ((uint32_t)(rc + 1) << 8) | child_depth;
@@ -777,11 +834,11 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
         emit = true;
         tag = 1;
       }
-    } else if (wn <= rmul(p_ratio, w) && rc + 1 < p_maxrc) {
+    } else if (wn <= rmul(p_ratio, w) && rc + 1 < (p_mode >> 8)) {
       kind = 1;
       n_push = 1;
       child_meta = ((uint32_t)(rc + 1) << 8) | child_depth;
-    } else if (p_split == 0) {
+    } else if ((p_mode & 3) == 0) {
       const iv xk = S.Xn[g][kk];
       mid_kk = imid(xk);
       if (!(mid_kk > xk.lo && mid_kk < -xk.nhi)) {
@@ -793,15 +850,15 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
       }
     }
   }
-  if (__ballot(p_split != 0) != 0) {
+  if (__ballot((p_mode & 3) != 0) != 0) {
     bool can = false;
-    if (alive && row_ok && p_split != 0) {
+    if (alive && row_ok && (p_mode & 3) != 0) {
       const iv xr = S.Xn[g][r];
       const double m = imid(xr);
       can = m > xr.lo && m < -xr.nhi;
     }
     split_mask = (uint32_t)group_bits<G>(__ballot(can), g);
-    if (alive && !emit && kind == 0 && p_split != 0) {
+    if (alive && !emit && kind == 0 && (p_mode & 3) != 0) {
       if (split_mask == 0) {
         emit = true;
         tag = 0;
@@ -842,9 +899,9 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
     unsigned long long* st = a.stats_sys;
     const uint32_t o8 = sysid * 8u;
     sys_add(st + kProcessed, o8, 1u, leader);
-    sys_add(st + kExclEval, o8, excluded ? 1u : 0u, leader);
+    sys_add(st + kExclEval, o8, (excluded || mv_excl) ? 1u : 0u, leader);
     sys_add(st + kExclHs, o8, hs_empty ? 1u : 0u, leader);
-    sys_add(st + kHsSkipped, o8, (active && !run) ? 1u : 0u, leader);
+    sys_add(st + kHsSkipped, o8, (active && !mv_excl && !run) ? 1u : 0u, leader);
     sys_add(st + kRecontract, o8, kind == 1 ? 1u : 0u, leader);
     sys_add(st + kBisected, o8, (kind == 2 || kind == 3) ? 1u : 0u, leader);
     sys_add(st + kEmitU, o8, (emit && tag == 1) ? 1u : 0u, leader);
@@ -857,12 +914,10 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
       sys_add(a.pending_sys, sysid, 0xFFFFFFFFu, dropped);
     }
   }
-  if (!STAGED) {
-    sc.add(kProcessed, (unsigned long long)(__popcll(__ballot(leader))));
-    sc.add(kExclEval, (unsigned long long)(__popcll(__ballot(leader && excluded))));
-  }
+  if (!STAGED) sc.add(kProcessed, (unsigned long long)(__popcll(__ballot(leader))));
+  sc.add(kExclEval, (unsigned long long)(__popcll(__ballot(leader && (excluded || mv_excl)))));
   sc.add(kExclHs, (unsigned long long)(__popcll(__ballot(leader && hs_empty))));
-  sc.add(kHsSkipped, (unsigned long long)(__popcll(__ballot(leader && active && !run))));
+  sc.add(kHsSkipped, (unsigned long long)(__popcll(__ballot(leader && active && !mv_excl && !run))));
   sc.add(kRecontract, (unsigned long long)(__popcll(__ballot(leader && kind == 1))));
   sc.add(kBisected, (unsigned long long)(__popcll(__ballot(leader && (kind == 2 || kind == 3)))));
   sc.add(kEmitU, (unsigned long long)(__popcll(__ballot(leader && emit && tag == 1))));
@@ -1074,7 +1129,7 @@ struct Occupancy {
   static constexpr int waves = (MULTI || G <= 8) ? 3 : 2;
 };
 
-template <int G, bool MULTI>
+template <int G, bool MULTI, bool VAR>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Occupancy<G, MULTI>::waves)))
 solve_kernel(SolveArgs a) {
   set_fp64_round_down();
@@ -1090,12 +1145,13 @@ solve_kernel(SolveArgs a) {
   // the wave's number within the workgroup, as a uniform (scalar) value
   const int wave_in_block = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
   char* const wave_base = smem + table_bytes + (size_t)wave_in_block * wave_scratch_bytes<G>(jn, a.jrs);
-  Scratch<G>* S = reinterpret_cast<Scratch<G>*>(wave_base);
-  const JView J{reinterpret_cast<iv*>(wave_base + ((sizeof(Scratch<G>) + 15) / 16) * 16), jn * a.jrs + 1, a.jrs};
+  Scratch<G>* S = reinterpret_cast<Scratch<G>*>(wave_base + kWaveHeader);
+  const JView J{reinterpret_cast<iv*>(wave_base + kWaveHeader + ((sizeof(Scratch<G>) + 15) / 16) * 16),
+                jn * a.jrs + 1, a.jrs};
   __syncthreads();
 
   constexpr int W = 64 / G;
-  const StepCounters sc{S->cnt};
+  const StepCounters sc{reinterpret_cast<unsigned long long*>(wave_base)};
   sc.clear();
   unsigned long long processed = 0, target = 0;
   Stage stg;
@@ -1146,7 +1202,8 @@ solve_kernel(SolveArgs a) {
         for (int t = 0; t < pop; ++t) {
           const unsigned long long tb = base + (unsigned long long)(t * W);
           if (tb >= cnt) break;
-          step_tile<G, MULTI>(a, T, *S, J, (long long)tb, (long long)cnt, cur, level, next_count, sc);
+          step_tile<G, MULTI, false, false, VAR>(a, T, *S, J, (long long)tb, (long long)cnt, cur, level, next_count,
+                                                 sc);
         }
         continue;
       }
@@ -1155,13 +1212,16 @@ solve_kernel(SolveArgs a) {
       for (;;) {
         const unsigned long long avail = stg.tail - stg.head;
         if (avail == 0 || (more && avail < (unsigned long long)W)) break;
-        step_tile<G, false, false, true>(a, T, *S, J, 0, 0, cur, level, next_count, sc, 0, false, nullptr, &stg);
+        step_tile<G, false, false, true, VAR>(a, T, *S, J, 0, 0, cur, level, next_count, sc, 0, false, nullptr,
+                                              &stg);
         stg.head += avail < (unsigned long long)W ? avail : (unsigned long long)W;
       }
       if (!more) break;
     }
     grid_barrier(a, target);
   }
+  // the rounding mode held to the end (see fp64_round_field)
+  if (fp64_round_field() != 2u && lane == 0) atomicCAS(&c->status, 0, kStatusModeLost);
   sc.flush(c->stats);
 }
 
@@ -1176,7 +1236,7 @@ solve_kernel(SolveArgs a) {
 // stepped; it reaches zero exactly when the search is over.  Every wait is
 // bounded (IBB_ERR_TIMEOUT, IBB_ERR_QUEUE_OVERFLOW).
 // ---------------------------------------------------------------------------
-template <int G>
+template <int G, bool VAR>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Occupancy<G, false>::waves)))
 queue_kernel(SolveArgs a) {
   set_fp64_round_down();
@@ -1188,11 +1248,12 @@ queue_kernel(SolveArgs a) {
   // the wave's number within the workgroup, as a uniform (scalar) value
   const int wave_in_block = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
   char* const wave_base = smem + table_bytes + (size_t)wave_in_block * wave_scratch_bytes<G>(jn, a.jrs);
-  Scratch<G>* S = reinterpret_cast<Scratch<G>*>(wave_base);
-  const JView J{reinterpret_cast<iv*>(wave_base + ((sizeof(Scratch<G>) + 15) / 16) * 16), jn * a.jrs + 1, a.jrs};
+  Scratch<G>* S = reinterpret_cast<Scratch<G>*>(wave_base + kWaveHeader);
+  const JView J{reinterpret_cast<iv*>(wave_base + kWaveHeader + ((sizeof(Scratch<G>) + 15) / 16) * 16),
+                jn * a.jrs + 1, a.jrs};
   __syncthreads();
 
-  const StepCounters sc{S->cnt};
+  const StepCounters sc{reinterpret_cast<unsigned long long*>(wave_base)};
   sc.clear();
   const int lane = __lane_id();
   const int g = lane / G;
@@ -1269,10 +1330,12 @@ queue_kernel(SolveArgs a) {
     for (;;) {
       const unsigned long long avail = stg.tail - stg.head;
       if (avail == 0 || (screen && avail < (unsigned long long)W)) break;
-      step_tile<G, false, true, true>(a, T, *S, J, 0, 0, 0, 0, nullptr, sc, 0, false, &ql, &stg);
+      step_tile<G, false, true, true, VAR>(a, T, *S, J, 0, 0, 0, 0, nullptr, sc, 0, false, &ql, &stg);
       stg.head += avail < (unsigned long long)W ? avail : (unsigned long long)W;
     }
   }
+  // the rounding mode held to the end (see fp64_round_field)
+  if (fp64_round_field() != 2u && lane == 0) atomicCAS(&c->status, 0, kStatusModeLost);
   sc.flush(c->stats);
   if (lane == 0) {
     if (ql.run_count && ql.run_depth < (unsigned)a.level_cap)
@@ -1472,6 +1535,47 @@ __global__ void seg_rank_kernel(const double* box, const uint32_t* tag, const ui
   out_tag[dst] = (uint8_t)ta;
 }
 
+// Serving: installs the requests admitted in one scheduling round (one
+// workgroup each): the compiled system into its slot, the slot's parameters,
+// counters and level bookkeeping, and the initial box at the end of its
+// bucket's current level.
+__global__ void admit_kernel(const AdmitRec* recs, const uint64_t* payload, uint64_t* blobs, int slot_words,
+                             SysParams* sp, int* nsys, int* status_sys, uint8_t* evict,
+                             unsigned long long* stats_sys, unsigned long long* slot_count,
+                             unsigned long long* cum_sys, unsigned long long* pending, unsigned long long* count_sys,
+                             int S) {
+  const AdmitRec& a = recs[blockIdx.x];
+  const int t = threadIdx.x;
+  uint64_t* dst = blobs + (size_t)a.slot * slot_words;
+  for (int i = t; i < a.nwords; i += blockDim.x) dst[i] = payload[a.blob_at + i];
+  if (t < 8) stats_sys[(size_t)a.slot * 8 + t] = 0ull;
+  if (t < 3) count_sys[(size_t)t * S + a.slot] = (t == a.level_slot) ? 1ull : 0ull;
+  if (t < 2) cum_sys[(size_t)t * S + a.slot] = 0ull;
+  if (t < a.G) {
+    a.front[((size_t)a.pos * a.G + t) * 2] = t < a.n ? a.lo[t] : 0.0;
+    a.front[((size_t)a.pos * a.G + t) * 2 + 1] = t < a.n ? -a.hi[t] : 0.0;
+  }
+  if (t == 0) {
+    sp[a.slot] = a.sp;
+    nsys[a.slot] = a.n;
+    status_sys[a.slot] = 0;
+    evict[a.slot] = 0;
+    slot_count[a.slot] = 0ull;
+    pending[a.slot] = 1ull;
+    a.meta[a.pos] = 0u;
+    a.sys[a.pos] = (uint32_t)a.slot;
+    if (a.set_count) a.ctrl->count[a.level_slot] = a.new_count;
+  }
+}
+
+// Serving: fails the given slots with `status`; the next pass drops their boxes.
+__global__ void evict_kernel(const int* slots, int count, uint8_t* evict, int* status_sys, int status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  evict[slots[i]] = 1;
+  status_sys[slots[i]] = status;
+}
+
 // Sorted output of one system's region (serving).
 __global__ void slot_sort_kernel(const double* box, const uint32_t* tag, const unsigned long long* slot_count,
                                  int slot, int cap, int n, double* out_lo, double* out_hi, uint8_t* out_tag) {
@@ -1505,20 +1609,31 @@ size_t scratch_bytes(int G, int jn, int rs) {
   }
 }
 
-const void* solve_kernel_ptr(int G, bool multi) {
+// The search kernel of a lane count: batches (multi) always support every
+// contractor and inclusion; one system gets the variant-free build unless
+// its parameters ask for Krawczyk or the mean-value test (var).
+const void* solve_kernel_ptr(int G, bool multi, bool var) {
   if (multi) {
     switch (G) {
-      case 2: return reinterpret_cast<const void*>(&solve_kernel<2, true>);
-      case 4: return reinterpret_cast<const void*>(&solve_kernel<4, true>);
-      case 8: return reinterpret_cast<const void*>(&solve_kernel<8, true>);
-      default: return reinterpret_cast<const void*>(&solve_kernel<16, true>);
+      case 2: return reinterpret_cast<const void*>(&solve_kernel<2, true, true>);
+      case 4: return reinterpret_cast<const void*>(&solve_kernel<4, true, true>);
+      case 8: return reinterpret_cast<const void*>(&solve_kernel<8, true, true>);
+      default: return reinterpret_cast<const void*>(&solve_kernel<16, true, true>);
+    }
+  }
+  if (var) {
+    switch (G) {
+      case 2: return reinterpret_cast<const void*>(&solve_kernel<2, false, true>);
+      case 4: return reinterpret_cast<const void*>(&solve_kernel<4, false, true>);
+      case 8: return reinterpret_cast<const void*>(&solve_kernel<8, false, true>);
+      default: return reinterpret_cast<const void*>(&solve_kernel<16, false, true>);
     }
   }
   switch (G) {
-    case 2: return reinterpret_cast<const void*>(&solve_kernel<2, false>);
-    case 4: return reinterpret_cast<const void*>(&solve_kernel<4, false>);
-    case 8: return reinterpret_cast<const void*>(&solve_kernel<8, false>);
-    default: return reinterpret_cast<const void*>(&solve_kernel<16, false>);
+    case 2: return reinterpret_cast<const void*>(&solve_kernel<2, false, false>);
+    case 4: return reinterpret_cast<const void*>(&solve_kernel<4, false, false>);
+    case 8: return reinterpret_cast<const void*>(&solve_kernel<8, false, false>);
+    default: return reinterpret_cast<const void*>(&solve_kernel<16, false, false>);
   }
 }
 
@@ -1551,12 +1666,20 @@ hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, long long count
   return hipGetLastError();
 }
 
-const void* queue_kernel_ptr(int G) {
+const void* queue_kernel_ptr(int G, bool var) {
+  if (var) {
+    switch (G) {
+      case 2: return reinterpret_cast<const void*>(&queue_kernel<2, true>);
+      case 4: return reinterpret_cast<const void*>(&queue_kernel<4, true>);
+      case 8: return reinterpret_cast<const void*>(&queue_kernel<8, true>);
+      default: return reinterpret_cast<const void*>(&queue_kernel<16, true>);
+    }
+  }
   switch (G) {
-    case 2: return reinterpret_cast<const void*>(&queue_kernel<2>);
-    case 4: return reinterpret_cast<const void*>(&queue_kernel<4>);
-    case 8: return reinterpret_cast<const void*>(&queue_kernel<8>);
-    default: return reinterpret_cast<const void*>(&queue_kernel<16>);
+    case 2: return reinterpret_cast<const void*>(&queue_kernel<2, false>);
+    case 4: return reinterpret_cast<const void*>(&queue_kernel<4, false>);
+    case 8: return reinterpret_cast<const void*>(&queue_kernel<8, false>);
+    default: return reinterpret_cast<const void*>(&queue_kernel<16, false>);
   }
 }
 
@@ -1608,6 +1731,23 @@ hipError_t launch_seg_sort(hipStream_t s, const double* box, const uint32_t* tag
 }  // namespace ibb
 
 namespace ibb {
+
+hipError_t launch_admit(hipStream_t s, const AdmitRec* recs, int count, const uint64_t* payload, uint64_t* blobs,
+                        int slot_words, SysParams* sp, int* nsys, int* status_sys, uint8_t* evict,
+                        unsigned long long* stats_sys, unsigned long long* slot_count, unsigned long long* cum_sys,
+                        unsigned long long* pending, unsigned long long* count_sys, int S) {
+  if (count > 0)
+    hipLaunchKernelGGL(admit_kernel, dim3(count), dim3(256), 0, s, recs, payload, blobs, slot_words, sp, nsys,
+                       status_sys, evict, stats_sys, slot_count, cum_sys, pending, count_sys, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_evict(hipStream_t s, const int* slots, int count, uint8_t* evict, int* status_sys, int status) {
+  if (count > 0)
+    hipLaunchKernelGGL(evict_kernel, dim3((count + 255) / 256), dim3(256), 0, s, slots, count, evict, status_sys,
+                       status);
+  return hipGetLastError();
+}
 
 hipError_t launch_slot_sort(hipStream_t s, const double* box, const uint32_t* tag,
                             const unsigned long long* slot_count, int slot, int cap, int n, double* out_lo,

@@ -49,11 +49,16 @@ struct Ctrl {
   int32_t pad[7];
 };
 
+// Status a search kernel records when it finds the FP64 rounding mode of its
+// wave changed (reported to the caller as IBB_ERR_DEVICE).
+constexpr int kStatusModeLost = -6;
+
 // Per-system search parameters of a batch (ibb_params in device form).
 struct SysParams {
   double tol, ratio, hs_max_width;
   long long max_boxes;
   int split_mode, max_rc;
+  int contractor, inclusion;
 };
 
 struct SolveArgs {
@@ -71,6 +76,8 @@ struct SolveArgs {
   double tol, ratio, hs_max_width;
   long long max_boxes;
   int split_mode, max_rc;
+  int contractor;  // 0 Hansen-Sengupta, 1 Krawczyk
+  int inclusion;   // 0 natural extension, 1 also the mean-value form
   int nblocks;
   int max_levels;           // stop after this many levels (0 = until the tree ends)
   long long timeout_ticks;  // device wall-clock ticks (100 MHz) a barrier may wait
@@ -102,6 +109,24 @@ struct SolveArgs {
   int slot_out_cap;  // > 0: each system emits into its own region of this many boxes
   unsigned long long* slot_out_count;  // [B] boxes emitted per system (regions)
   unsigned long long* pending_sys;     // [B] boxes per system still to step (or null)
+  const uint8_t* evict;                // [B] nonzero: the system's boxes are dropped when loaded (or null)
+};
+
+// Serving: admission record of one request, uploaded with the others of its
+// scheduling round; the admission kernel installs the request in its slot and
+// appends its initial box to its bucket's current level.
+struct AdmitRec {
+  int32_t slot, n, G, nwords;
+  long long blob_at;  // word offset of the compiled system in the round's payload
+  SysParams sp;
+  double* front;      // the bucket's current level; the initial box goes to index pos
+  uint32_t* meta;
+  uint32_t* sys;
+  long long pos;
+  Ctrl* ctrl;         // with set_count: the bucket's count of that level becomes new_count
+  unsigned long long new_count;
+  int32_t level_slot, set_count;
+  double lo[kMaxN], hi[kMaxN];
 };
 
 // Layout of the diagnostic dump of one step (doubles), n = system size:

@@ -33,6 +33,16 @@ __device__ __forceinline__ void set_fp64_round_down() {
   asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2" ::: "memory");
 }
 
+// The FP64/FP16 rounding field of the wave's MODE register (2 = toward
+// -infinity).  The search kernels read it back when their waves finish: a
+// value other than 2 means some code or event changed the mode under the
+// kernel, and the search reports an error instead of a possibly wrong list.
+__device__ __forceinline__ unsigned fp64_round_field() {
+  unsigned v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_MODE, 2, 2)" : "=s"(v));
+  return v;
+}
+
 // ---- one rounded instruction each; R(x) = x rounded toward -infinity ----
 __device__ __forceinline__ double radd(double a, double b) {  // R(a + b)
   double r;

@@ -14,11 +14,15 @@ pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 # the dense n=6 and banded n=12 workloads, seeds 0..4 (up to 16.8 million
-# tree nodes per solve)
+# tree nodes per solve); seed 0 also with the Krawczyk contractor and with the
+# mean-value exclusion test
 CASES = {}
 for _k in range(5):
-    CASES[f"dense6_s{_k}"] = (lambda k: lambda: W.dense_planted(k))(_k)
-    CASES[f"banded12_s{_k}"] = (lambda k: lambda: W.banded(k))(_k)
+    CASES[f"dense6_s{_k}"] = ((lambda k: lambda: W.dense_planted(k))(_k), {})
+    CASES[f"banded12_s{_k}"] = ((lambda k: lambda: W.banded(k))(_k), {})
+for _name, _mk in (("dense6", W.dense_planted), ("banded12", W.banded)):
+    CASES[f"{_name}_s0_krawczyk"] = ((lambda mk: lambda: mk(0))(_mk), {"contractor": 1})
+    CASES[f"{_name}_s0_meanvalue"] = ((lambda mk: lambda: mk(0))(_mk), {"inclusion": 1})
 
 
 def _load(name):
@@ -32,9 +36,10 @@ def _load(name):
 def test_full_size_matches_stored_oracle(gpu_ctx, name):
     import paper_1802_00330_amd as P
     g = _load(name)
-    s = CASES[name]()
+    make, kw = CASES[name]
+    s = make()
     print(f"[fullsize] {name}: {g['stats']['processed']} nodes", flush=True)
-    r = P.solve(gpu_ctx, s)
+    r = P.solve(gpu_ctx, s, **kw)
     assert r.status == g["status"] == 0
     assert r.stats == g["stats"]
     lo = np.array([[float.fromhex(v) for v in row] for row in g["lo"]]).reshape(-1, s.n)

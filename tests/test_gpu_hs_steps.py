@@ -58,17 +58,21 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("contractor", [0, 1], ids=["hansen_sengupta", "krawczyk"])
 @pytest.mark.parametrize("name,make,center", CASES)
-def test_single_steps_match_oracle(gpu_ctx, oracle_lib, name, make, center):
+def test_single_steps_match_oracle(gpu_ctx, oracle_lib, name, make, center, contractor):
+    """Hansen-Sengupta (eq 17-22) and Krawczyk (eq 15-16; the trace's N holds
+    K(X)) steps on 150 boxes around a root."""
     import paper_1802_00330_amd as P
     s = make()
     c = center()
     rng = np.random.default_rng(7)
     first = None
     nbad = 0
+    params = P.make_params(s.tol, contractor=contractor)
     for k, (lo, hi) in enumerate(_boxes_around(c, rng, 150)):
-        dev = P.ibb_debug_step(gpu_ctx, s, lo, hi)
-        st, ref = oracle_lib.hs_trace(s, lo, hi)
+        dev = P.ibb_debug_step(gpu_ctx, s, lo, hi, params)
+        st, ref = oracle_lib.hs_trace(s, lo, hi, contractor=contractor)
         if dev[6 * s.n * s.n + 8 * s.n + 3] != 1.0 and st != oracle_lib.HS_SKIPPED:
             # the device excluded the box before contracting it: nothing to compare
             continue

@@ -40,12 +40,70 @@ SPLIT_ALL_CASES = {
 }
 
 
+@pytest.mark.parametrize("threshold", [0.5, 0.125])
+@pytest.mark.parametrize("name", ["product3", "product4", "dense4"])
+def test_paper_mode_contraction_after_a_width(gpu_ctx, oracle_lib, name, threshold):
+    """The paper's driver: every coordinate bisected, the contraction only on
+    boxes no wider than a threshold (branch and bound alone in the first
+    rounds, Tab. 1 then Tab. 2)."""
+    s = SPLIT_ALL_CASES[name]()
+    gpu, ref = _both(gpu_ctx, oracle_lib, s, split_mode=1, hs_max_width=threshold)
+    assert ref.stats["hs_skipped"] > 0
+    assert_same(gpu, ref, f"{name} ALL, contraction below {threshold}")
+
+
 @pytest.mark.parametrize("name", sorted(SPLIT_ALL_CASES))
 def test_split_all_with_contraction(gpu_ctx, oracle_lib, name):
     s = SPLIT_ALL_CASES[name]()
     gpu, ref = _both(gpu_ctx, oracle_lib, s, split_mode=1)
     assert ref.stats["excluded_hs"] + ref.stats["recontracted"] > 0  # the contraction acted
     assert_same(gpu, ref, f"{name} ALL")
+
+
+# the Krawczyk contractor (eq 15-16) and the mean-value exclusion test, alone
+# and together, on the whole search
+VARIANTS = {"krawczyk": {"contractor": 1}, "mean_value": {"inclusion": 1},
+            "krawczyk_mean_value": {"contractor": 1, "inclusion": 1}}
+VARIANT_SYSTEMS = {
+    "circle_line": lambda: W.circle_line(),
+    "product3": lambda: W.product_linear([4, 3], n=3),
+    "product5": lambda: W.product_linear([4, 5], n=5),
+    "dense4": lambda: W.dense_planted(0, n=4, n_terms=6, max_deg=2),
+    "dense5_cubic": lambda: W.dense_planted(0, n=5, n_terms=8, max_deg=3),
+    "banded8": lambda: W.banded(0, n=8, tol=1e-8),
+    "batch_member11": lambda: W.batch_planted(0, indices=[11])[0],
+}
+
+
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+@pytest.mark.parametrize("name", sorted(VARIANT_SYSTEMS))
+def test_contractor_and_inclusion_variants(gpu_ctx, oracle_lib, name, variant):
+    s = VARIANT_SYSTEMS[name]()
+    gpu, ref = _both(gpu_ctx, oracle_lib, s, **VARIANTS[variant])
+    assert_same(gpu, ref, f"{name} {variant}")
+
+
+def test_dense_n6_subbox_variants(gpu_ctx, oracle_lib):
+    s = W.dense_planted(0)
+    r = s.roots[0]
+    for kw in VARIANTS.values():
+        gpu, ref = _both(gpu_ctx, oracle_lib, s, lo=r - 0.14, hi=r + 0.26, **kw)
+        assert_same(gpu, ref, f"dense n=6 sub-box {kw}")
+
+
+def test_batch_members_with_different_variants(gpu_ctx, oracle_lib):
+    """A batch whose members use different contractors and inclusions: each
+    member equals its oracle solve."""
+    import paper_1802_00330_amd as P
+    systems = [W.product_linear([4, 3], n=3), W.dense_planted(0, n=4, n_terms=6, max_deg=2),
+               W.banded(0, n=8, tol=1e-8), W.circle_line(), W.product_linear([4, 5], n=5),
+               W.batch_planted(0, indices=[11])[0]]
+    kws = [{}, {"contractor": 1}, {"inclusion": 1}, {"contractor": 1, "inclusion": 1}, {"contractor": 1},
+           {"inclusion": 1}]
+    params = [P.make_params(s.tol, **kw) for s, kw in zip(systems, kws)]
+    res = P.ibb_solve_batch(gpu_ctx, systems, params)
+    for s, kw, r in zip(systems, kws, res):
+        assert_same(r, oracle_lib.solve(s, **kw), f"{s.name} {kw}")
 
 
 def test_host_pointer_entry_point(gpu_ctx, oracle_lib):
