@@ -138,16 +138,24 @@ def batched_leg(ctx, P, W, count, budget, plain_sample, cpu_members, log):
                           and np.array_equal(a.tag, b.tag) for a, b in zip(plain, sb) if a.status == P.OK)
     agree = agree and all(a.status == b.status and a.stats == b.stats and np.array_equal(a.lo, b.lo)
                           for a, b in zip(sb, res[:plain_sample]))
-    # the same batch recorded once and replayed from its graph
-    plan = P.BatchPlan(ctx, systems, params)
-    plan.run()  # first replay
-    t = time.perf_counter()
-    rres = plan.run()
-    rdt = time.perf_counter() - t
-    rkms = P.ibb_last_kernel_ms(ctx)
-    plan.close()
-    same = all(a.status == b.status and a.stats == b.stats and np.array_equal(a.lo, b.lo)
-               and np.array_equal(a.hi, b.hi) and np.array_equal(a.tag, b.tag) for a, b in zip(rres, res))
+    log(f"[bench] batch: {done} of {count} completed, {nodes} tree nodes in {dt:.3f} s "
+        f"(first call {first_dt:.3f} s)")
+    # the same batch recorded once and replayed from its graph (a plan is one
+    # batch: one whose frontier exceeds the device memory is reported, not split)
+    try:
+        plan = P.BatchPlan(ctx, systems, params)
+        plan.run()  # first replay
+        t = time.perf_counter()
+        rres = plan.run()
+        rdt = time.perf_counter() - t
+        rkms = P.ibb_last_kernel_ms(ctx)
+        plan.close()
+        same = all(a.status == b.status and a.stats == b.stats and np.array_equal(a.lo, b.lo)
+                   and np.array_equal(a.hi, b.hi) and np.array_equal(a.tag, b.tag) for a, b in zip(rres, res))
+        replay = {"seconds": rdt, "device_ms": rkms, "boxes_per_s": nodes / rdt, "solves_per_s": done / rdt,
+                  "identical_to_batch": bool(same)}
+    except RuntimeError as e:
+        replay = {"error": str(e)}
     out = {"systems": count, "budget_nodes_per_system": budget, "completed": done, "over_budget": over,
            "completed_by_n": {str(k): {"members": v[0], "completed": v[1]} for k, v in sorted(by_n.items())},
            "autotune": {"seconds": tune_s, "sample_per_class": 128,
@@ -161,8 +169,7 @@ def batched_leg(ctx, P, W, count, budget, plain_sample, cpu_members, log):
                             "batch_seconds": sdt, "batch_boxes_per_s": sn / sdt, "batch_solves_per_s": pdone / sdt,
                             "batched_vs_plain_solves_per_s": pdt / sdt,
                             "identical": bool(agree)},
-           "graph_replay": {"seconds": rdt, "device_ms": rkms, "boxes_per_s": nodes / rdt,
-                            "solves_per_s": done / rdt, "identical_to_batch": bool(same)}}
+           "graph_replay": replay}
     if cpu_members > 0:
         import oracle
         model, cores = host_cpu()
@@ -308,7 +315,7 @@ def variants_leg(ctx, P, W, batch_members, log):
     return out
 
 
-def single_solves(ctx, P, W, steps, log):
+def single_solves(ctx, P, W, steps, log, cpu_nodes=100_000):
     """Per-solve latency and boxes/s of the circle/line system (n=2) and the
     banded n=12 system (seed 0, tol 1e-10), workspace resident on the device."""
     import numpy as np
@@ -344,6 +351,19 @@ def single_solves(ctx, P, W, steps, log):
                      "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
                      "kernel_ms_mean": float(np.mean(kms)), "boxes_per_s": nodes / float(np.median(lat)),
                      "same_as_solve": bool(dict(zip(P.STATS_FIELDS, (int(v) for v in inf[2:10]))) == r.stats)}
+        if cpu_nodes > 0:
+            # the oracle on one core: the whole solve, or its first cpu_nodes tree nodes
+            import oracle
+            t = time.perf_counter()
+            o = oracle.solve(s, max_boxes=cpu_nodes)
+            odt = time.perf_counter() - t
+            done = o.stats["processed"] if o.status == 0 else cpu_nodes
+            model, _ = host_cpu()
+            out[name]["cpu_baseline"] = {"value": done / odt, "unit": "boxes/s", "cores": 1, "cpu": model,
+                                         "kind": "oracle",
+                                         "sample": ("the whole solve" if o.status == 0 else
+                                                    f"first {done} tree nodes (last-in-first-out order)") +
+                                                   f", one thread, {odt:.2f} s"}
         log(f"[bench] {name}: {out[name]}")
     return out
 

@@ -170,6 +170,12 @@ int ibb_solve(ibb_ctx* ctx, const ibb_system* sys, const double* lo, const doubl
  * own status (IBB_OK, IBB_ERR_INVALID_ARG, IBB_ERR_BUDGET; a failed system
  * returns no boxes) and stats[b] its counters (levels and max_frontier are 0)
  * when stats is not NULL.  Each system's result equals ibb_solve on it alone.
+ * Device memory: the frontier is sized from the autotuner's measured widths
+ * (below) within the free device memory (or the bound ibb_batch_set_memory
+ * sets); a batch whose frontier does not fit is solved in parts, halving the
+ * member range until each part fits, with the same results; a single member
+ * whose widest level alone exceeds the memory fails alone with
+ * IBB_ERR_QUEUE_OVERFLOW.
  * Returns IBB_OK, IBB_ERR_OUTPUT_CAPACITY (out_off filled: out_off[B] is the
  * required capacity) or a device error. */
 int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const double* lo,
@@ -186,7 +192,9 @@ int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const do
  * arguments and meaning).  A frontier or output overflow re-records the graph
  * with larger capacities.  IBB_ERR_UNSUPPORTED if the runtime cannot record
  * the launches.  The systems and boxes are copied at creation; one plan runs
- * one batch at a time. */
+ * one batch at a time.  A plan is one batch, never split: a frontier beyond
+ * the free device memory (or the context's bound) fails ibb_batch_plan_run
+ * with IBB_ERR_NO_MEMORY. */
 typedef struct ibb_batch_plan ibb_batch_plan;
 int ibb_batch_plan_create(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const double* lo,
                           const double* hi, const ibb_params* params, ibb_batch_plan** plan);
@@ -230,6 +238,13 @@ typedef struct ibb_batch_config {
   double front_per_member;
 } ibb_batch_config;
 
+/* Bound, in bytes, on the device workspace of ibb_solve_batch and of plans
+ * created afterwards (0, the default: the free device memory); a batch whose
+ * frontier needs more is solved in parts.  Frees the context's batch
+ * workspace when it exceeds the new bound.  IBB_ERR_INVALID_ARG for a null
+ * context or a negative size. */
+int ibb_batch_set_memory(ibb_ctx* ctx, int64_t bytes);
+
 /* Current configuration of class cls (0..3) into *out.  IBB_ERR_INVALID_ARG
  * for a bad class or null pointer. */
 int ibb_batch_get_config(ibb_ctx* ctx, int32_t cls, ibb_batch_config* out);
@@ -272,8 +287,9 @@ int ibb_batch_tune(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const dou
  *       are failed with IBB_ERR_QUEUE_OVERFLOW, alone (their boxes are dropped,
  *       the other solves go on);
  *   (4) enqueues one pass of `levels_per_quantum` tree levels of every bucket
- *       and returns without waiting for it, so that host work between calls
- *       overlaps the device's.
+ *       and, while requests wait for admission, returns without waiting for
+ *       it, so that host work between calls overlaps the device's (with none
+ *       waiting it harvests the pass before returning).
  * A solve keeps its boxes resident on the device until it finishes, and its
  * result is identical to ibb_solve on it alone.  Only IBB_SPLIT_WIDEST is
  * served. */

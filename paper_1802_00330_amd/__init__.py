@@ -41,7 +41,7 @@ EXPORTS = ("ibb_ctx_create", "ibb_ctx_destroy", "ibb_strerror", "ibb_params_defa
            "ibb_server_create", "ibb_server_destroy", "ibb_server_submit", "ibb_server_step", "ibb_server_poll",
            "ibb_server_cancel", "ibb_server_pending", "ibb_round", "ibb_batch_plan_create", "ibb_batch_plan_run",
            "ibb_batch_plan_destroy", "ibb_batch_get_config", "ibb_batch_set_config", "ibb_batch_tune",
-           "ibb_solve_noalloc", "ibb_server_finished", "ibb_backtrack")
+           "ibb_solve_noalloc", "ibb_server_finished", "ibb_backtrack", "ibb_batch_set_memory")
 
 
 class IbbSystem(C.Structure):
@@ -137,6 +137,7 @@ def load_library(path: str = LIB_PATH):
     L.ibb_batch_set_config.restype = C.c_int
     L.ibb_batch_set_config.argtypes = [p, i32, C.POINTER(IbbBatchConfig)]
     L.ibb_batch_tune.restype, L.ibb_batch_tune.argtypes = C.c_int, [p, i32, p, p, p, p, i32]
+    L.ibb_batch_set_memory.restype, L.ibb_batch_set_memory.argtypes = C.c_int, [p, i64]
     L.ibb_round.restype = C.c_int
     L.ibb_round.argtypes = [p, C.POINTER(IbbSystem), C.POINTER(IbbParams), i64, p, p, p, p, p, p, i64,
                             C.POINTER(C.c_int64), p, p, p, i64, C.POINTER(C.c_int64), C.POINTER(IbbStats)]
@@ -488,6 +489,14 @@ def ibb_batch_set_config(ctx: Context, cls: int, lanes: int, tiles_per_claim: in
     st = load_library().ibb_batch_set_config(ctx.handle, int(cls), C.byref(c))
     if st != OK:
         raise RuntimeError(f"ibb_batch_set_config: {ibb_strerror(st)}")
+
+
+def ibb_batch_set_memory(ctx: Context, nbytes: int):
+    """Bound the device workspace of batch solves (0: the free device memory);
+    a batch whose frontier needs more is solved in parts."""
+    st = load_library().ibb_batch_set_memory(ctx.handle, int(nbytes))
+    if st != OK:
+        raise RuntimeError(f"ibb_batch_set_memory: {ibb_strerror(st)}")
 
 
 def ibb_batch_tune(ctx: Context, systems, params=None, sample: int = 256):

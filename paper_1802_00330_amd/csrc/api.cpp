@@ -257,6 +257,7 @@ struct ibb_ctx {
   void* bws = nullptr;  // batch workspace
   size_t bws_bytes = 0;
   long long batch_fcap = 0;  // frontier capacity the last batch needed
+  long long batch_mem = 0;   // bound on the batch workspace in bytes (0: free device memory)
   // launch configuration of each lane-count class of batch members
   ibb_batch_config batch_cfg[4] = {{2, 1, 0, 0, 0.0}, {4, 1, 0, 0, 0.0}, {8, 1, 0, 0, 0.0}, {16, 1, 0, 0, 0.0}};
   // schedule autotuner: best kernel time per (n, T, TD, split mode) and
@@ -832,18 +833,17 @@ int batch_finish(const BatchHost& h, char* w, const BatchLayout& L, long long oc
   return IBB_OK;
 }
 
-// First frontier capacity of a batch.  A level of a member holds at most half
-// of the member's node budget and the members' widest levels do not all
-// coincide, so a quarter of the summed budgets (each counted up to 2^20),
-// within [4 M, 64 M] boxes, or what an earlier batch on the context needed.
 // Frontier capacity (boxes) of a batch's first attempt.  When the autotuner has
 // measured every lane-count class present (ibb_batch_tune: the widest level
 // of a class's sample launch per member), the capacity is that width times
 // the members of each launch, with a margin of a half, for the widest launch;
-// otherwise a quarter of the members' node budgets (each at most 2^20).  At
-// least what an earlier batch on this context needed.
+// otherwise a quarter of the members' node budgets (each at most 2^20; a
+// level of a member holds at most half of its budget and the members' widest
+// levels do not all coincide).  At least what an earlier batch on this context
+// needed.  *measured (if not null): the unclamped estimate from measured
+// widths, 0 without one.
 long long batch_first_fcap(const ibb_ctx* ctx, int32_t B, const ibb_system* systems, const ibb_params* params,
-                           const int32_t* status, const ibb_batch_config* cfg) {
+                           const int32_t* status, const ibb_batch_config* cfg, long long* measured = nullptr) {
   double sum = 0.0, launch[4] = {0, 0, 0, 0};
   bool tuned = true;
   for (int b = 0; b < B; ++b) {
@@ -855,9 +855,12 @@ long long batch_first_fcap(const ibb_ctx* ctx, int32_t B, const ibb_system* syst
     launch[lanes_class(cfg[cls].lanes)] += w;
   }
   long long f;
+  if (measured) *measured = 0;
   if (tuned) {
     const double widest = std::max(std::max(launch[0], launch[1]), std::max(launch[2], launch[3]));
-    f = std::min<long long>(1LL << 28, std::max<long long>(1LL << 16, (long long)(1.5 * widest)));
+    const double est = std::min(1.5 * widest, 1e15);
+    if (measured) *measured = (long long)est;
+    f = std::min<long long>(1LL << 28, std::max<long long>(1LL << 16, (long long)est));
   } else {
     f = std::min<long long>(1LL << 26, std::max<long long>(1LL << 22, (long long)(sum / 4.0)));
   }
@@ -878,12 +881,32 @@ bool batch_outputs_ok(int64_t cap, const double* out_lo, const double* out_hi, c
 
 namespace {
 
+// Largest frontier capacity whose batch layout fits in the device memory that
+// is free now plus `reusable` bytes (the workspace a larger layout replaces),
+// keeping 5 % of it and 512 MiB for other allocations, and within the
+// context's bound on the batch workspace when one is set; at least 2^16.
+long long batch_fcap_limit(const ibb_ctx* ctx, int B, size_t words, long long ocap, size_t reusable) {
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return 1LL << 16;
+  double avail = ((double)free_b + (double)reusable) * 0.95 - (double)(512ull << 20);
+  if (ctx->batch_mem > 0) avail = std::min(avail, (double)ctx->batch_mem);
+  const double base = (double)batch_layout(B, words, 0, ocap).total;
+  const double per = ((double)batch_layout(B, words, 1LL << 20, ocap).total - base) / (double)(1 << 20);
+  const double f = (avail - base) / per;
+  if (!(f >= (double)(1 << 16))) return 1LL << 16;
+  return std::min<long long>(1LL << 28, (long long)f);
+}
+
+constexpr int kSplit = 1;  // internal: the batch's frontier does not fit, solve it in parts
+
 // One eager batch solve under the launch configurations cfg[4]; *ms (if not
-// null) receives the device time of the batch's device work.
-int solve_batch_with(ibb_ctx* ctx, const ibb_batch_config* cfg, int32_t B, const ibb_system* systems,
+// null) receives the device time of the batch's device work.  Returns kSplit
+// when the frontier the batch needs exceeds what device memory holds and the
+// batch has more than one member.
+int solve_batch_part(ibb_ctx* ctx, const ibb_batch_config* cfg, int32_t B, const ibb_system* systems,
                      const double* lo, const double* hi, const ibb_params* params, double* out_lo, double* out_hi,
                      uint8_t* out_tag, int64_t cap, int64_t* out_off, int32_t* status, ibb_stats* stats,
-                     float* ms, long long* widest = nullptr) {
+                     float* ms, long long* widest) {
   if (hipSetDevice(ctx->device) != hipSuccess) return IBB_ERR_DEVICE;
   if (ms) *ms = 0.0f;
   BatchHost h;
@@ -894,8 +917,14 @@ int solve_batch_with(ibb_ctx* ctx, const ibb_batch_config* cfg, int32_t B, const
     return IBB_OK;
   }
   // capacities sized for the batch up front (an overflow re-runs the whole batch)
-  long long fcap = batch_first_fcap(ctx, B, systems, params, status, cfg);
+  long long measured = 0;
+  long long fcap = batch_first_fcap(ctx, B, systems, params, status, cfg, &measured);
   long long ocap = std::max<long long>(1LL << 15, 16LL * B);
+  const long long fmax = batch_fcap_limit(ctx, B, h.words, ocap, ctx->bws_bytes);
+  // measured widths that cannot fit: split before running (an estimate from
+  // node budgets only caps the first attempt)
+  if (measured > fmax && B > 1) return kSplit;
+  fcap = std::min(fcap, fmax);
   hipStream_t s = ctx->stream;
   for (int attempt = 0; attempt < 10; ++attempt) {
     const BatchLayout L = batch_layout(B, h.words, fcap, ocap);
@@ -916,7 +945,15 @@ int solve_batch_with(ibb_ctx* ctx, const ibb_batch_config* cfg, int32_t B, const
                       widest);
     if (st) return st;
     if (grow_f) {
-      fcap *= 4;
+      if (fcap >= fmax) {
+        if (B > 1) return kSplit;
+        // a single member whose widest level exceeds the memory: it fails alone
+        status[0] = IBB_ERR_QUEUE_OVERFLOW;
+        out_off[0] = out_off[1] = 0;
+        if (stats) std::memset(stats, 0, sizeof(ibb_stats));
+        return IBB_OK;
+      }
+      fcap = std::min(fcap * 4, fmax);
       continue;
     }
     if (grow_o) {
@@ -930,6 +967,41 @@ int solve_batch_with(ibb_ctx* ctx, const ibb_batch_config* cfg, int32_t B, const
   return IBB_ERR_NO_MEMORY;
 }
 
+// A batch solve that splits itself in halves (recursively) while its frontier
+// does not fit in device memory.  Each member's result depends on the member
+// alone, so the parts' results, placed back to back, are the batch's.  *ms
+// and widest[] accumulate over the parts.
+int solve_batch_with(ibb_ctx* ctx, const ibb_batch_config* cfg, int32_t B, const ibb_system* systems,
+                     const double* lo, const double* hi, const ibb_params* params, double* out_lo, double* out_hi,
+                     uint8_t* out_tag, int64_t cap, int64_t* out_off, int32_t* status, ibb_stats* stats,
+                     float* ms, long long* widest = nullptr) {
+  const int st = solve_batch_part(ctx, cfg, B, systems, lo, hi, params, out_lo, out_hi, out_tag, cap, out_off,
+                                  status, stats, ms, widest);
+  if (st != kSplit) return st;
+  const int B1 = B / 2, B2 = B - B1;
+  float ms1 = 0.0f, ms2 = 0.0f;
+  long long w1[4] = {0, 0, 0, 0}, w2[4] = {0, 0, 0, 0};
+  const int st1 = solve_batch_with(ctx, cfg, B1, systems, lo, hi, params, out_lo, out_hi, out_tag, cap, out_off,
+                                   status, stats, ms ? &ms1 : nullptr, w1);
+  if (st1 != IBB_OK && st1 != IBB_ERR_OUTPUT_CAPACITY) return st1;
+  // the second half writes behind the first (or only sizes its output when
+  // the first did not fit)
+  const int64_t base = out_off[B1];
+  const bool room = st1 == IBB_OK;
+  std::vector<int64_t> off2((size_t)B2 + 1);
+  const int st2 = solve_batch_with(
+      ctx, cfg, B2, systems + B1, lo + (size_t)B1 * kMaxN, hi + (size_t)B1 * kMaxN, params + B1,
+      room ? out_lo + (size_t)base * kMaxN : nullptr, room ? out_hi + (size_t)base * kMaxN : nullptr,
+      room ? out_tag + base : nullptr, room ? cap - base : 0, off2.data(), status + B1, stats ? stats + B1 : nullptr,
+      ms ? &ms2 : nullptr, w2);
+  if (st2 != IBB_OK && st2 != IBB_ERR_OUTPUT_CAPACITY) return st2;
+  for (int b = 1; b <= B2; ++b) out_off[B1 + b] = base + off2[b];
+  if (ms) *ms = ms1 + ms2;
+  if (widest)
+    for (int q = 0; q < 4; ++q) widest[q] = w1[q] + w2[q];
+  return (st1 == IBB_OK && st2 == IBB_OK) ? IBB_OK : IBB_ERR_OUTPUT_CAPACITY;
+}
+
 }  // namespace
 
 extern "C" int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* systems, const double* lo,
@@ -940,6 +1012,20 @@ extern "C" int ibb_solve_batch(ibb_ctx* ctx, int32_t B, const ibb_system* system
     return IBB_ERR_INVALID_ARG;
   return solve_batch_with(ctx, ctx->batch_cfg, B, systems, lo, hi, params, out_lo, out_hi, out_tag, cap, out_off,
                           status, stats, nullptr);
+}
+
+extern "C" int ibb_batch_set_memory(ibb_ctx* ctx, int64_t bytes) {
+  if (!ctx || bytes < 0) return IBB_ERR_INVALID_ARG;
+  if (bytes > 0 && ctx->bws_bytes > (size_t)bytes) {
+    // batch solves are synchronous: nothing runs on the workspace now
+    if (hipSetDevice(ctx->device) != hipSuccess) return IBB_ERR_DEVICE;
+    hipFree(ctx->bws);
+    ctx->bws = nullptr;
+    ctx->bws_bytes = 0;
+  }
+  ctx->batch_mem = bytes;
+  ctx->batch_fcap = 0;  // capacities learned under another bound no longer apply
+  return IBB_OK;
 }
 
 extern "C" int ibb_batch_get_config(ibb_ctx* ctx, int32_t cls, ibb_batch_config* out) {
@@ -1138,7 +1224,10 @@ extern "C" int ibb_batch_plan_create(ibb_ctx* ctx, int32_t B, const ibb_system* 
   }
   p->fcap = batch_first_fcap(ctx, B, systems, params, p->status0.data(), ctx->batch_cfg);
   p->ocap = std::max<long long>(1LL << 15, 16LL * B);
-  if (!st && p->h.any) st = plan_build(p);
+  if (!st && p->h.any) {
+    p->fcap = std::min(p->fcap, batch_fcap_limit(ctx, B, p->h.words, p->ocap, 0));
+    st = plan_build(p);
+  }
   if (st) {
     ibb_batch_plan_destroy(p);
     return st;
@@ -1171,7 +1260,12 @@ extern "C" int ibb_batch_plan_run(ibb_batch_plan* p, double* out_lo, double* out
                           out_off, status, stats, &grow_f, &grow_o);
     if (st) return st;
     if (!grow_f && !grow_o) return IBB_OK;
-    if (grow_f) p->fcap *= 4;
+    if (grow_f) {
+      // a plan is not split: a frontier beyond device memory fails the run
+      const long long fmax = batch_fcap_limit(ctx, B, p->h.words, p->ocap, p->L.total);
+      if (p->fcap >= fmax) return IBB_ERR_NO_MEMORY;
+      p->fcap = std::min(p->fcap * 4, fmax);
+    }
     if (grow_o) p->ocap = grow_o;
     st = plan_build(p);
     if (st) return st;
@@ -2210,6 +2304,15 @@ int ibb_server_step(ibb_server* sv) {
         hipEventRecord(sv->pass_done, s) != hipSuccess)
       return IBB_ERR_DEVICE;
     sv->in_flight = true;
+    // with nothing waiting for admission there is no host work to overlap:
+    // harvest this pass at once (its solves finish one round earlier)
+    if (sv->queue.empty()) {
+      if (hipEventSynchronize(sv->pass_done) != hipSuccess) return IBB_ERR_DEVICE;
+      sv->in_flight = false;
+      const int more = harvest(sv);
+      if (more < 0) return more;
+      finished += more;
+    }
   }
   return finished;
 }
