@@ -159,36 +159,74 @@ __global__ void prep_kernel(uint64_t* blobs, const long long* blob_off, int B) {
 // Interval evaluation (Def. 1): monomials as products of powers, variables
 // ascending, coefficient last; equations as sums of terms in stored order.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ iv eval_monomial(uint64_t f, const iv* X) {
-  iv m = ipow(X[f & 0xF], (int)((f >> 4) & 0xF));
+//
+// The powers of a box's coordinates are staged in LDS before an evaluation:
+// the lane owning coordinate v writes X_v^2 and (when E = 3) X_v^3, each the
+// value ipow returns, so that a factor x_v^e with e <= E is one LDS read
+// instead of a chain set up per term; larger exponents are evaluated by ipow
+// in place.  The values are those of ipow in every case, so the evaluation is
+// unchanged bit for bit.
+template <int E>
+struct Powers {
+  const iv* p1;  // X
+  const iv* p2;  // X^2
+  const iv* p3;  // X^3 (E = 3)
+};
+
+template <int E>
+__device__ __forceinline__ iv factor_power(const Powers<E>& P, uint64_t f) {
+  const int v = (int)(f & 0xF), e = (int)((f >> 4) & 0xF);
+  if (E == 1) return ipow(P.p1[v], e);
+  const iv* src = (e == 2) ? P.p2 : ((E == 3 && e == 3) ? P.p3 : P.p1);
+  iv x = src[v];
+  if (e > E) x = ipow(x, e);
+  return x;
+}
+
+// The owner lane of coordinate r stages its powers (called by lanes r < n of
+// the groups that evaluate; followed by a wave-level LDS sync).  E = 1 stages
+// nothing: every factor is evaluated in place.
+template <int E>
+__device__ __forceinline__ void stage_powers(const Powers<E>& P, int r) {
+  if (E == 1) return;
+  const iv x = P.p1[r];
+  const_cast<iv*>(P.p2)[r] = ipow(x, 2);
+  if (E == 3) const_cast<iv*>(P.p3)[r] = ipow(x, 3);
+}
+
+template <int E>
+__device__ __forceinline__ iv eval_monomial(uint64_t f, const Powers<E>& P) {
+  iv m = factor_power<E>(P, f);
   f >>= 8;
   while (f & 0xF0) {
-    m = imul(m, ipow(X[f & 0xF], (int)((f >> 4) & 0xF)));
+    m = imul(m, factor_power<E>(P, f));
     f >>= 8;
   }
   return m;
 }
 
-__device__ __forceinline__ iv eval_equation(const LTable& t, int i, const iv* X) {
+template <int E>
+__device__ __forceinline__ iv eval_equation(const LTable& t, int i, const Powers<E>& P) {
   const int a = t.eq_off[i], b = t.eq_off[i + 1];
   iv acc{0.0, 0.0};
   for (int q = a; q < b; ++q) {
     const uint64_t f = t.fac[q];
     const double c = t.coef[q];
-    iv v = f ? pmul(c, eval_monomial(f, X)) : point_iv(c);
+    iv v = f ? pmul(c, eval_monomial<E>(f, P)) : point_iv(c);
     acc = (q == a) ? v : iadd(acc, v);
   }
   return acc;
 }
 
 // d f_i / d x_k over X (Alg. 3, first step); [0,0] without terms.
-__device__ __forceinline__ iv eval_partial(const LTable& t, int i, int k, const iv* X) {
+template <int E>
+__device__ __forceinline__ iv eval_partial(const LTable& t, int i, int k, const Powers<E>& P) {
   const int a = t.der_off[i * t.n + k], b = t.der_off[i * t.n + k + 1];
   iv acc{0.0, -0.0};
   for (int q = a; q < b; ++q) {
     const uint64_t f = t.dfac[q];
     const iv c = t.dco[q];
-    iv v = f ? imul(c, eval_monomial(f, X)) : c;
+    iv v = f ? imul(c, eval_monomial<E>(f, P)) : c;
     acc = (q == a) ? v : iadd(acc, v);
   }
   return acc;
@@ -501,9 +539,19 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
 
   // ---- exclusion test (Def. 2): some F_i(X) excludes 0
   bool excl_row = false;
-  if (!STAGED && valid && !proven && row_ok) {
-    const iv f = eval_equation(T, r, S.X[g]);
-    excl_row = f.lo > 0.0 || f.nhi > 0.0;
+  if (!STAGED) {
+    // powers of X in the contracted-box and X - x rows, free until the
+    // contraction (batches of up to 16 unknowns: none, which keeps their
+    // register budget)
+    constexpr int E = (MULTI && G == 16) ? 1 : 3;
+    const Powers<E> PX{S.X[g], S.Xn[g], S.D[g]};
+    if (valid && !proven && row_ok) stage_powers<E>(PX, r);
+    wave_lds_sync();
+    if (valid && !proven && row_ok) {
+      const iv f = eval_equation<E>(T, r, PX);
+      excl_row = f.lo > 0.0 || f.nhi > 0.0;
+    }
+    wave_lds_sync();
   }
   const bool excluded = group_bits<G>(__ballot(excl_row), g) != 0;
   const bool active = valid && !excluded;
@@ -518,18 +566,30 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
 
   bool hs_empty = false, hs_unique = false, run = false, mv_excl = false;
   if (__ballot(do_j) != 0) {
-    // H1, H8: expansion point x = mid X and X - x
+    // H1: expansion point x = mid X, with its powers in the contracted-box
+    // and X - x rows (free until the contraction and until H8)
+    // (batches of up to 16 unknowns stage none, which keeps their register budget)
+    constexpr int EC = (MULTI && G == 16) ? 1 : 3, EX = (MULTI && G == 16) ? 1 : 2;
+    const Powers<EC> PC{S.Xc[g], S.Xn[g], S.D[g]};
     if (do_j && row_ok) {
-      const iv x = S.X[g][r];
-      const double m = imid(x);
-      S.Xc[g][r] = point_iv(m);
-      S.D[g][r] = isub(x, point_iv(m));
+      S.Xc[g][r] = point_iv(imid(S.X[g][r]));
+      stage_powers<EC>(PC, r);
     }
     wave_lds_sync();
-    // H2, H3: row r of J(X); F_r at the degenerate box [x, x]
+    // H3: F_r at the degenerate box [x, x]
+    if (do_j && row_ok) S.Fc[g][r] = eval_equation<EC>(T, r, PC);
+    wave_lds_sync();
+    // H8: X - x; the square of X in the contracted-box row
+    const Powers<EX> PX{S.X[g], S.Xn[g], nullptr};
     if (do_j && row_ok) {
-      for (int k = 0; k < n; ++k) J(g, r, k) = eval_partial(T, r, k, S.X[g]);
-      S.Fc[g][r] = eval_equation(T, r, S.Xc[g]);
+      const iv x = S.X[g][r];
+      S.D[g][r] = isub(x, S.Xc[g][r]);
+      stage_powers<EX>(PX, r);
+    }
+    wave_lds_sync();
+    // H2: row r of J(X)
+    if (do_j && row_ok) {
+      for (int k = 0; k < n; ++k) J(g, r, k) = eval_partial<EX>(T, r, k, PX);
       if (dbg) {
         for (int k = 0; k < n; ++k) {
           dbg[dbg_off_J(n) + (r * n + k) * 2] = J(g, r, k).lo;
@@ -1066,8 +1126,12 @@ __device__ __forceinline__ void screen_tile(const SolveArgs& a, const LTable& T,
   wave_lds_sync();
   if (QUEUE) queue_after_load(a, idx, valid, meta, r, ql);
   bool excl_row = false;
+  // powers of X in the contracted-box and X - x rows (not in use while screening)
+  const Powers<3> PX{S.X[g], S.Xn[g], S.D[g]};
+  if (valid && !proven && row_ok) stage_powers<3>(PX, r);
+  wave_lds_sync();
   if (valid && !proven && row_ok) {
-    const iv f = eval_equation(T, r, S.X[g]);
+    const iv f = eval_equation<3>(T, r, PX);
     excl_row = f.lo > 0.0 || f.nhi > 0.0;
   }
   const bool excluded = group_bits<G>(__ballot(excl_row), g) != 0;
