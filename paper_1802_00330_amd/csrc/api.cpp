@@ -2282,7 +2282,9 @@ int ibb_server_step(ibb_server* sv) {
     a.jrs = geo.jrs;
     a.jn = jn;
     // the grid barrier counts arrivals from zero in every pass
-    if (launch_fill_u64(s, &b.ctrl->bar, 1, 0ull) != hipSuccess) return IBB_ERR_DEVICE;
+    if (launch_fill_u64(s, &b.ctrl->bar, 1, 0ull) != hipSuccess ||
+        launch_fill_u64(s, b.ctrl->sync, (long long)(sizeof(b.ctrl->sync) / 8), 0ull) != hipSuccess)
+      return IBB_ERR_DEVICE;
     void* args[] = {&a};
     if (hipLaunchCooperativeKernel(fn, dim3(geo.blocks), dim3(64 * geo.waves), args, (unsigned)geo.lds, s) !=
         hipSuccess)
@@ -2294,7 +2296,7 @@ int ibb_server_step(ibb_server* sv) {
   if (any) {
     const Back back = back_view(sv);
     for (int q = 0; q < 4; ++q)
-      if (hipMemcpyAsync(&back.ctrls[q], sv->bk[q].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess)
+      if (hipMemcpyAsync(&back.ctrls[q], sv->bk[q].ctrl, kCtrlCounterBytes, hipMemcpyDeviceToHost, s) != hipSuccess)
         return IBB_ERR_DEVICE;
     if (hipMemcpyAsync(back.pending, sv->pending, 8ull * S, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(back.stats, sv->stats_sys, 64ull * S, hipMemcpyDeviceToHost, s) != hipSuccess ||

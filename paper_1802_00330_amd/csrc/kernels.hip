@@ -1159,28 +1159,59 @@ __device__ __forceinline__ void screen_tile(const SolveArgs& a, const LTable& T,
 }
 
 // ---------------------------------------------------------------------------
-// Grid barrier between levels.  Every wait is bounded: after timeout_ticks of
-// the 100 MHz device clock the barrier records IBB_ERR_TIMEOUT and returns, and
-// every later wait returns as soon as it sees a non-zero status.
+// Grid barrier between levels.  The boxes a level writes are read by
+// workgroups on other XCDs, whose L2 caches are not coherent with this one's,
+// so each workgroup writes its XCD's L2 back before it arrives and
+// invalidates its caches after the release: once per workgroup (its first
+// thread, after every wave's stores have left the CU), not once per wave,
+// which would repeat the write-back and invalidation thousands of times per
+// level.  Arrivals are counted per group of workgroups (blockIdx % 8, one
+// counter line each); the last arrival of a group arrives at the global
+// counter, and the last group raises every group's release flag, which the
+// group's workgroups poll.  `gen` counts the barriers of the launch (the
+// barrier lines are zero at launch).  Every wait is bounded: after
+// timeout_ticks of the 100 MHz device clock the barrier records
+// IBB_ERR_TIMEOUT and returns, and every later wait returns as soon as it
+// sees a non-zero status.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void grid_barrier(const SolveArgs& a, unsigned long long& target) {
-  __threadfence();
+__device__ __forceinline__ void grid_barrier(const SolveArgs& a, unsigned long long& gen) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
-  target += (unsigned long long)a.nblocks;
+  ++gen;
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(&a.ctrl->bar, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    Ctrl* c = a.ctrl;
+    unsigned long long* const arrive = c->sync;
+    unsigned long long* const flag = c->sync + kSyncGroups * kSyncStride;
+    const unsigned x = blockIdx.x % (unsigned)kSyncGroups;
+    const unsigned long long groups =
+        a.nblocks < kSyncGroups ? (unsigned long long)a.nblocks : (unsigned long long)kSyncGroups;
+    const unsigned long long members =
+        ((unsigned long long)a.nblocks - x + (unsigned long long)kSyncGroups - 1ull) / (unsigned long long)kSyncGroups;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned long long old =
+        __hip_atomic_fetch_add(&arrive[x * kSyncStride], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1ull == members * gen) {
+      // the group's last arrival carries the group's writes on
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      const unsigned long long g = __hip_atomic_fetch_add(&c->bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (g + 1ull == groups * gen) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        for (int y = 0; y < kSyncGroups; ++y)
+          __hip_atomic_store(&flag[y * kSyncStride], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
     const unsigned long long t0 = wall_clock64();
-    while (__hip_atomic_load(&a.ctrl->bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(&flag[x * kSyncStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
       __builtin_amdgcn_s_sleep(2);
-      if (__hip_atomic_load(&a.ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      if (__hip_atomic_load(&c->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
       if ((long long)(wall_clock64() - t0) > a.timeout_ticks) {
-        atomicCAS(&a.ctrl->status, 0, -8);
+        atomicCAS(&c->status, 0, -8);
         break;
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  __threadfence();
 }
 
 // Resident waves per SIMD the register allocation aims for: three for one
@@ -1217,7 +1248,7 @@ solve_kernel(SolveArgs a) {
   constexpr int W = 64 / G;
   const StepCounters sc{reinterpret_cast<unsigned long long*>(wave_base)};
   sc.clear();
-  unsigned long long processed = 0, target = 0;
+  unsigned long long processed = 0, gen = 0;
   Stage stg;
   {
     const size_t wave = (size_t)blockIdx.x * (blockDim.x / 64) + (size_t)wave_in_block;
@@ -1226,6 +1257,9 @@ solve_kernel(SolveArgs a) {
   }
   const int lane = __lane_id();
   Ctrl* c = a.ctrl;
+  const unsigned long long nwaves = (unsigned long long)a.nblocks * (blockDim.x / 64);
+  const unsigned long long wave_gid =
+      (unsigned long long)blockIdx.x * (blockDim.x / 64) + (unsigned long long)wave_in_block;
   for (int level = a.level0;; ++level) {
     const unsigned long long cnt =
         __hip_atomic_load(&c->count[level % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1254,12 +1288,24 @@ solve_kernel(SolveArgs a) {
     }
     const int cur = level & 1;
     unsigned long long* next_count = &c->count[(level + 1) % 3];
-    // batches: a wave claims `pop` consecutive tiles per atomic
+    // batches: a wave claims `pop` consecutive tiles per atomic.  A wave's
+    // first claim of a level is static (the claim numbered by its global wave
+    // index); later ones come from the level's counter, counted from the
+    // first claim no wave holds.  A wave without a static claim touches no
+    // counter, so a narrow level costs its few busy waves, not one atomic per
+    // wave of the grid.
     const int pop = (MULTI && a.tiles_per_claim > 1) ? a.tiles_per_claim : 1;
+    const unsigned long long claim_w = (unsigned long long)(W * pop);
+    bool first = true;
     for (;;) {
       unsigned long long base = 0;
-      if (lane == 0) base = atomicAdd(&c->claim[level % 3], (unsigned long long)(W * pop));
-      base = __shfl(base, 0, 64);
+      if (first) {
+        base = wave_gid * claim_w;
+        first = false;
+      } else {
+        if (lane == 0) base = atomicAdd(&c->claim[level % 3], claim_w);
+        base = __shfl(base, 0, 64) + nwaves * claim_w;
+      }
       const bool more = base < cnt;
       if (MULTI) {
         if (!more) break;
@@ -1282,7 +1328,7 @@ solve_kernel(SolveArgs a) {
       }
       if (!more) break;
     }
-    grid_barrier(a, target);
+    grid_barrier(a, gen);
   }
   // the rounding mode held to the end (see fp64_round_field)
   if (fp64_round_field() != 2u && lane == 0) atomicCAS(&c->status, 0, kStatusModeLost);
@@ -1494,7 +1540,7 @@ __global__ void finalize_kernel(const Ctrl* c, long long out_cap, long long* inf
 __global__ void init_kernel(Ctrl* c, double* front0, uint32_t* meta0, const double* lo, const double* hi,
                             int n, int G) {
   const int t = threadIdx.x;
-  if (t < (int)(sizeof(Ctrl) / 8)) reinterpret_cast<unsigned long long*>(c)[t] = 0ull;
+  for (int i = t; i < (int)(sizeof(Ctrl) / 8); i += blockDim.x) reinterpret_cast<unsigned long long*>(c)[i] = 0ull;
   if (t < G) {
     front0[2 * t] = t < n ? lo[t] : 0.0;
     front0[2 * t + 1] = t < n ? -hi[t] : 0.0;
@@ -1547,7 +1593,8 @@ __global__ void batch_init_kernel(Ctrl* c, double* front0, uint32_t* meta0, uint
                                   unsigned long long* count_sys, int B) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (blockIdx.x == 0) {
-    if (threadIdx.x < (int)(sizeof(Ctrl) / 8)) reinterpret_cast<unsigned long long*>(c)[threadIdx.x] = 0ull;
+    for (int i = threadIdx.x; i < (int)(sizeof(Ctrl) / 8); i += blockDim.x)
+      reinterpret_cast<unsigned long long*>(c)[i] = 0ull;
     __syncthreads();
     if (threadIdx.x == 0) c->count[0] = (unsigned long long)m;
   }

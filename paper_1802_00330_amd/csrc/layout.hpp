@@ -33,6 +33,10 @@ static_assert(sizeof(SysDesc) == 128, "SysDesc size");
 
 // Control block of one solve (device memory, zero-initialised by the host
 // except count[0] = 1).
+// Grid barrier: groups of workgroups and the u64 stride of their lines.
+constexpr int kSyncGroups = 8;
+constexpr int kSyncStride = 16;
+
 struct Ctrl {
   unsigned long long count[3];   // frontier size of level L in count[L % 3]
   unsigned long long claim[3];   // next unclaimed box of level L in claim[L % 3]
@@ -47,7 +51,14 @@ struct Ctrl {
   unsigned long long qhead, qtail, pending, qspare;
   int32_t status;
   int32_t pad[7];
+  // grid barrier of a persistent launch (zero at launch): the arrivals of each
+  // group of workgroups (blockIdx % 8) and each group's release flag, each in
+  // a 128-byte line of its own
+  unsigned long long sync[2 * kSyncGroups * kSyncStride];
 };
+
+// Bytes of a Ctrl before its barrier lines (the counters a host reads back).
+constexpr size_t kCtrlCounterBytes = offsetof(Ctrl, sync);
 
 // Status a search kernel records when it finds the FP64 rounding mode of its
 // wave changed (reported to the caller as IBB_ERR_DEVICE).
