@@ -30,6 +30,27 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Work-queue records go between XCDs, whose L2 caches are not coherent with
+// each other.  Instead of a device-scope release (an L2 write-back) per push
+// and an acquire (an L2 invalidation) per claimed tile, the records are
+// stored and loaded at device scope (relaxed device-scope atomic accesses,
+// which are written through to, and read from, the point of coherence); a
+// producer waits for its record stores to complete (s_waitcnt vmcnt(0))
+// before it stores the slot's sequence word, and a consumer loads a record
+// only after it has read that word.
+__device__ __forceinline__ void store_coherent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_coherent(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_coherent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_coherent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int G>
 __device__ __forceinline__ uint64_t group_bits(uint64_t ballot, int g) {
   constexpr uint64_t gm = (G >= 64) ? ~0ull : ((1ull << G) - 1ull);
@@ -411,9 +432,10 @@ __device__ __forceinline__ void queue_after_load(const SolveArgs& a, long long i
                                                  QueueLocal* ql) {
   const int lane = __lane_id();
   const unsigned long long qmask = (unsigned long long)a.front_cap - 1ull;
-  // the slot is read (the loads above are complete once this wave's release
-  // fence returns): free it for the item one ring length later
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  // the slot is read once this wave's loads of it have returned (a
+  // workgroup-scope fence does not wait for them): free it for the item one
+  // ring length later
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   if (valid && r == 0)
     __hip_atomic_store(&a.qseq[(unsigned long long)idx & qmask], (unsigned long long)idx + qmask + 1ull,
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -528,9 +550,9 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
     const int buf = QUEUE ? 0 : cur;
     if (row_ok) {
       const double* src = a.front[buf] + (at * G + r) * 2;
-      S.X[g][r] = iv{src[0], src[1]};
+      S.X[g][r] = QUEUE ? iv{load_coherent(src), load_coherent(src + 1)} : iv{src[0], src[1]};
     }
-    meta = a.meta[buf][at];
+    meta = QUEUE ? load_coherent(&a.meta[buf][at]) : a.meta[buf][at];
   }
   const bool proven = meta & 1u;
   const int rc = (int)((meta >> 8) & 0xFF);
@@ -1063,19 +1085,26 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
         if (kind == 2 && r == kk) y = c ? iv{mid_kk, x.nhi} : iv{x.lo, -mid_kk};
         if (kind == 3 && mine) y = ((c >> q) & 1) ? iv{m, x.nhi} : iv{x.lo, -m};
         double* dst = a.front[buf] + (at * G + r) * 2;
-        dst[0] = y.lo;
-        dst[1] = y.nhi;
+        if (QUEUE) {
+          store_coherent(dst, y.lo);
+          store_coherent(dst + 1, y.nhi);
+        } else {
+          dst[0] = y.lo;
+          dst[1] = y.nhi;
+        }
       }
       if (r == 0) {
-        a.meta[buf][at] = kind == 1 ? child_meta : child_depth;
+        if (QUEUE) store_coherent(&a.meta[buf][at], kind == 1 ? child_meta : child_depth);
+        else a.meta[buf][at] = kind == 1 ? child_meta : child_depth;
         if (MULTI) a.sys[buf][at] = sysid;
       }
       pushed = c + 1;
     }
   }
   if (QUEUE) {
-    // publish: the box stores above become visible before the slot flags
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // publish: the boxes were stored at device scope (coherent stores, see
+    // store_coherent); they are complete before the slot flags are stored
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     if (r == 0)
       for (int c = 0; c < pushed; ++c)
         __hip_atomic_store(&a.qseq[(o + (unsigned long long)c) & qmask], o + (unsigned long long)c + 1ull,
@@ -1118,9 +1147,9 @@ __device__ __forceinline__ void screen_tile(const SolveArgs& a, const LTable& T,
     const int buf = QUEUE ? 0 : cur;
     if (row_ok) {
       const double* src = a.front[buf] + (at * G + r) * 2;
-      S.X[g][r] = iv{src[0], src[1]};
+      S.X[g][r] = QUEUE ? iv{load_coherent(src), load_coherent(src + 1)} : iv{src[0], src[1]};
     }
-    meta = a.meta[buf][at];
+    meta = QUEUE ? load_coherent(&a.meta[buf][at]) : a.meta[buf][at];
   }
   const bool proven = meta & 1u;
   wave_lds_sync();
@@ -1431,8 +1460,7 @@ queue_kernel(SolveArgs a) {
     }
     if (stop) break;
     if (screen) {
-      // the published boxes are read after this point
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      // the published boxes are read after this point, with coherent loads
       screen_tile<G, true>(a, T, *S, 0, 0, 0, sc, slot, full, &ql, stg);
       if (full) slot = -1;
     }
