@@ -30,6 +30,8 @@ WORKLOADS = {
                 "box [-1,1]^12, tol 1e-10, one solve per step",
 }
 FP64_PEAK = 78.6e12  # MI355X FP64 vector, FLOP/s
+# solves the schedule autotuner times (two per schedule) before it settles
+TUNE_SOLVES = 4
 HBM_PEAK = 8.0e12    # bytes/s
 
 
@@ -290,8 +292,8 @@ def variants_leg(ctx, P, W, batch_members, log):
     for name, s in (("dense_n6_s0", W.dense_planted(0)), ("banded_n12_s0", W.banded(0))):
         out[name] = {}
         for v, kw in variants.items():
-            P.solve(ctx, s, **kw)  # each variant's schedule is tuned on its first two solves
-            P.solve(ctx, s, **kw)
+            for _ in range(TUNE_SOLVES):  # each variant's schedule is tuned on its first solves
+                P.solve(ctx, s, **kw)
             r = P.solve(ctx, s, **kw)
             ms = P.ibb_last_kernel_ms(ctx)
             out[name][v] = {"status": r.status, "tree_nodes": r.stats.get("processed"),
@@ -322,8 +324,9 @@ def single_solves(ctx, P, W, steps, log, cpu_nodes=100_000):
     import torch
     out = {}
     for name, s in (("circle_line_n2", W.circle_line()), ("banded_n12_s0", W.banded(0))):
-        r = P.solve(ctx, s)  # sizes the buffers, times both schedules on the first two
-        P.solve(ctx, s)
+        r = P.solve(ctx, s)  # sizes the buffers; the schedule autotuner times its candidates
+        for _ in range(TUNE_SOLVES - 1):
+            P.solve(ctx, s)
         fcap = 1
         while fcap < 4 * max(r.max_frontier, 256):
             fcap *= 2
@@ -423,7 +426,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2,
-                    help="solves before the timed ones (the schedule autotuner times its two candidates here)")
+                    help="untimed solves before the timed ones (after the set-up solves in which the schedule "
+                         "autotuner times its two candidates)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--system", choices=("dense6", "banded12"), default="dense6",
                     help="workload of the timed solves: the dense n=6 system (tol 1e-8, the headline) or the "
@@ -498,7 +502,12 @@ def main():
         break
     log(f"[bench] warm solve: {int(inf[2])} nodes, {int(inf[1])} boxes, {int(inf[10])} levels, "
         f"widest level {int(inf[11])}, frontier cap {fcap}")
-    for _ in range(max(0, args.warmup - 1)):
+    # set-up: the schedule autotuner times two launches of each schedule
+    # (the sizing solve above was the first), then the warm-up solves
+    for _ in range(TUNE_SOLVES - 1):
+        P.ibb_solve_async(ctx, s, params, ws, fcap, ocap, olo, ohi, otag, info, stream=stream)
+        stream.synchronize()
+    for _ in range(args.warmup):
         P.ibb_solve_async(ctx, s, params, ws, fcap, ocap, olo, ohi, otag, info, stream=stream)
         stream.synchronize()
     torch.cuda.synchronize()

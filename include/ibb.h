@@ -69,9 +69,10 @@ extern "C" {
 #define IBB_SCHEDULE_QUEUE 0
 #define IBB_SCHEDULE_LEVELS 1
 /* IBB_SCHEDULE_AUTO (default): per system shape (n, terms, derivative terms,
- * split mode, contractor, inclusion) the context times the search kernel once
- * with each schedule,
- * then keeps the faster one.  Results do not depend on the choice. */
+ * split mode, contractor, inclusion) the context times the search kernel
+ * twice with each schedule (the first launch on fresh device memory runs
+ * slower than later ones), then keeps the faster one.  Results do not depend
+ * on the choice. */
 #define IBB_SCHEDULE_AUTO 2
 
 /* Contraction step applied to the boxes that pass the exclusion test.

@@ -262,7 +262,12 @@ struct ibb_ctx {
   ibb_batch_config batch_cfg[4] = {{2, 1, 0, 0, 0.0}, {4, 1, 0, 0, 0.0}, {8, 1, 0, 0, 0.0}, {16, 1, 0, 0, 0.0}};
   // schedule autotuner: best kernel time per (n, T, TD, split mode) and
   // schedule, and the shape / schedule of the launch ev0..ev1 last bracketed
-  std::map<std::tuple<int, int, int, int>, std::array<float, 2>> tune;
+  // per shape: the fastest time of each schedule and how many launches it timed
+  struct TuneEntry {
+    float ms[2] = {-1.0f, -1.0f};
+    int n[2] = {0, 0};
+  };
+  std::map<std::tuple<int, int, int, int>, TuneEntry> tune;
   bool tune_pending = false;
   std::tuple<int, int, int, int> tune_key;
   int tune_sched = 0;
@@ -425,11 +430,17 @@ int launch_search(ibb_ctx* ctx, const Compiled& c, const ibb_params* p, char* ws
 
 // Schedule of a full solve.  With IBB_SCHEDULE_AUTO, the kernel time of the
 // previous single-system launch is first credited to its shape and schedule;
-// a shape still missing a measurement gets the schedule it lacks.
+// a shape with fewer than kTuneSamples timed launches of a schedule gets that
+// schedule (the first launch on fresh device memory is slower than the
+// following ones, so one sample each can pick the slower schedule), then the
+// faster of the two.
+constexpr int kTuneSamples = 2;
+
 int resolve_schedule(ibb_ctx* ctx, const Compiled& c, const ibb_params* p) {
   if (ctx->tune_pending) {
     auto it = ctx->tune.find(ctx->tune_key);
-    const bool learning = it != ctx->tune.end() && (it->second[0] < 0 || it->second[1] < 0);
+    const bool learning =
+        it != ctx->tune.end() && (it->second.n[0] < kTuneSamples || it->second.n[1] < kTuneSamples);
     long long status = 0;
     if (learning) {
       hipEventSynchronize(ctx->done);
@@ -439,8 +450,9 @@ int resolve_schedule(ibb_ctx* ctx, const Compiled& c, const ibb_params* p) {
     if (status == 0 && hipEventQuery(ctx->ev1) == hipSuccess) {
       float ms = 0.0f;
       if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) == hipSuccess && it != ctx->tune.end()) {
-        float& slot = it->second[ctx->tune_sched];
+        float& slot = it->second.ms[ctx->tune_sched];
         slot = slot < 0 ? ms : std::min(slot, ms);
+        ++it->second.n[ctx->tune_sched];
       }
     }
     ctx->tune_pending = false;
@@ -448,12 +460,13 @@ int resolve_schedule(ibb_ctx* ctx, const Compiled& c, const ibb_params* p) {
   // shape key: size, terms, derivative terms, and the split, contractor and inclusion (their kernels differ)
   const auto key = std::make_tuple(c.n, c.T, c.TD, p->split_mode | (p->contractor << 2) | (p->inclusion << 3));
   auto it = ctx->tune.find(key);
-  if (it == ctx->tune.end()) it = ctx->tune.emplace(key, std::array<float, 2>{-1.0f, -1.0f}).first;
+  if (it == ctx->tune.end()) it = ctx->tune.emplace(key, ibb_ctx::TuneEntry{}).first;
   int sched = p->schedule;
   if (sched == IBB_SCHEDULE_AUTO) {
-    if (it->second[0] < 0) sched = IBB_SCHEDULE_QUEUE;
-    else if (it->second[1] < 0) sched = IBB_SCHEDULE_LEVELS;
-    else sched = it->second[1] < it->second[0] ? IBB_SCHEDULE_LEVELS : IBB_SCHEDULE_QUEUE;
+    const auto& e = it->second;
+    if (e.n[0] < kTuneSamples) sched = IBB_SCHEDULE_QUEUE;
+    else if (e.n[1] < kTuneSamples) sched = IBB_SCHEDULE_LEVELS;
+    else sched = e.ms[1] < e.ms[0] ? IBB_SCHEDULE_LEVELS : IBB_SCHEDULE_QUEUE;
   }
   // credited when the next solve is enqueued (see above)
   ctx->tune_key = key;
