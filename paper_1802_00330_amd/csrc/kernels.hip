@@ -253,6 +253,40 @@ __device__ __forceinline__ iv eval_partial(const LTable& t, int i, int k, const 
   return acc;
 }
 
+// Row i of J(X) into J(g, i, 0..n-1): the derivative terms of the row are
+// walked in one loop (columns ascending, each column's terms in stored order,
+// summed as eval_partial does), so the lanes of a wave, whose rows have
+// different numbers of terms per column but similar totals, run one loop of
+// about the same length instead of n loops of different lengths.
+template <int E, typename JV>
+__device__ __forceinline__ void eval_jacobian_row(const LTable& t, int i, const Powers<E>& P, const JV& J, int g) {
+  const int n = t.n;
+  const int* off = t.der_off + i * n;
+  const int q1 = off[n];
+  int k = 0;
+  int kend = off[1];
+  iv acc{0.0, -0.0};
+  bool have = false;
+  for (int q = off[0]; q < q1; ++q) {
+    while (q >= kend) {  // column k is complete (or has no terms)
+      J(g, i, k) = acc;
+      acc = iv{0.0, -0.0};
+      have = false;
+      ++k;
+      kend = off[k + 1];
+    }
+    const uint64_t f = t.dfac[q];
+    const iv c = t.dco[q];
+    const iv v = f ? imul(c, eval_monomial<E>(f, P)) : c;
+    acc = have ? iadd(acc, v) : v;
+    have = true;
+  }
+  for (; k < n; ++k) {
+    J(g, i, k) = acc;
+    acc = iv{0.0, -0.0};
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Per-wave scratch in LDS for the W = 64/G boxes of a tile.  Each box's rows
 // are padded by one element so that the boxes of a wave (and, in the
@@ -611,7 +645,7 @@ __device__ __forceinline__ void step_tile(const SolveArgs& a, const LTable& Tl, 
     wave_lds_sync();
     // H2: row r of J(X)
     if (do_j && row_ok) {
-      for (int k = 0; k < n; ++k) J(g, r, k) = eval_partial<EX>(T, r, k, PX);
+      eval_jacobian_row<EX>(T, r, PX, J, g);
       if (dbg) {
         for (int k = 0; k < n; ++k) {
           dbg[dbg_off_J(n) + (r * n + k) * 2] = J(g, r, k).lo;
