@@ -88,6 +88,33 @@ def oracle_pool(jobs, cores):
     return res, time.perf_counter() - t
 
 
+def same_members_leg(ctx, P, sample, sparams, res):
+    """The first members solved two ways: the plain solver one system per call,
+    and one batch of just these members (same budget)."""
+    import numpy as np
+    t = time.perf_counter()
+    plain = [P.ibb_solve(ctx, s, p) for s, p in zip(sample, sparams)]
+    pdt = time.perf_counter() - t
+    pn = sum(r.stats["processed"] for r in plain)
+    P.ibb_solve_batch(ctx, sample, sparams)
+    t = time.perf_counter()
+    sb = P.ibb_solve_batch(ctx, sample, sparams)
+    sdt = time.perf_counter() - t
+    sn = sum(r.stats["processed"] for r in sb)
+    pdone = sum(1 for r in plain if r.status == P.OK)
+    # finished members agree bit for bit; a budget error stops the two
+    # schedules at different points, so only the status is compared there
+    agree = all((a.status == P.OK) == (b.status == P.OK) for a, b in zip(plain, sb))
+    agree = agree and all(a.stats == b.stats and np.array_equal(a.lo, b.lo) and np.array_equal(a.hi, b.hi)
+                          and np.array_equal(a.tag, b.tag) for a, b in zip(plain, sb) if a.status == P.OK)
+    agree = agree and all(a.status == b.status and a.stats == b.stats and np.array_equal(a.lo, b.lo)
+                          for a, b in zip(sb, res[:len(sample)]))
+    return {"systems": len(sample), "completed": pdone, "tree_nodes": pn,
+            "plain_seconds": pdt, "plain_boxes_per_s": pn / pdt, "plain_solves_per_s": pdone / pdt,
+            "batch_seconds": sdt, "batch_boxes_per_s": sn / sdt, "batch_solves_per_s": pdone / sdt,
+            "batched_vs_plain_solves_per_s": pdt / sdt, "identical": bool(agree)}
+
+
 def batched_leg(ctx, P, W, count, budget, plain_sample, cpu_members, log):
     """4096 planted systems (n 2..12, degree 2..4) in one batched pass; the
     plain per-system solver and the batch on the same sample of members; the
@@ -122,24 +149,10 @@ def batched_leg(ctx, P, W, count, budget, plain_sample, cpu_members, log):
         c[1] += r.status == P.OK
     # the same members two ways: the plain solver one system per call, and
     # one batch of just these members (same budget)
+    same_members = None
     sample, sparams = systems[:plain_sample], params[:plain_sample]
-    t = time.perf_counter()
-    plain = [P.ibb_solve(ctx, s, p) for s, p in zip(sample, sparams)]
-    pdt = time.perf_counter() - t
-    pn = sum(r.stats["processed"] for r in plain)
-    P.ibb_solve_batch(ctx, sample, sparams)
-    t = time.perf_counter()
-    sb = P.ibb_solve_batch(ctx, sample, sparams)
-    sdt = time.perf_counter() - t
-    sn = sum(r.stats["processed"] for r in sb)
-    pdone = sum(1 for r in plain if r.status == P.OK)
-    # finished members agree bit for bit; a budget error stops the two
-    # schedules at different points, so only the status is compared there
-    agree = all((a.status == P.OK) == (b.status == P.OK) for a, b in zip(plain, sb))
-    agree = agree and all(a.stats == b.stats and np.array_equal(a.lo, b.lo) and np.array_equal(a.hi, b.hi)
-                          and np.array_equal(a.tag, b.tag) for a, b in zip(plain, sb) if a.status == P.OK)
-    agree = agree and all(a.status == b.status and a.stats == b.stats and np.array_equal(a.lo, b.lo)
-                          for a, b in zip(sb, res[:plain_sample]))
+    if plain_sample > 0:
+        same_members = same_members_leg(ctx, P, sample, sparams, res)
     log(f"[bench] batch: {done} of {count} completed, {nodes} tree nodes in {dt:.3f} s "
         f"(first call {first_dt:.3f} s)")
     # the same batch recorded once and replayed from its graph (a plan is one
@@ -166,11 +179,7 @@ def batched_leg(ctx, P, W, count, budget, plain_sample, cpu_members, log):
                                     for c in tuned]},
            "tree_nodes": nodes, "seconds": dt, "first_call_seconds": first_dt, "kernel_ms": kms,
            "boxes_per_s": nodes / dt, "solves_per_s": done / dt, "members_per_s": count / dt,
-           "same_members": {"systems": plain_sample, "completed": pdone, "tree_nodes": pn,
-                            "plain_seconds": pdt, "plain_boxes_per_s": pn / pdt, "plain_solves_per_s": pdone / pdt,
-                            "batch_seconds": sdt, "batch_boxes_per_s": sn / sdt, "batch_solves_per_s": pdone / sdt,
-                            "batched_vs_plain_solves_per_s": pdt / sdt,
-                            "identical": bool(agree)},
+           "same_members": same_members,
            "graph_replay": replay}
     if cpu_members > 0:
         import oracle
