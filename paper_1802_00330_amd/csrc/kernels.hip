@@ -239,25 +239,13 @@ __device__ __forceinline__ iv eval_equation(const LTable& t, int i, const Powers
   return acc;
 }
 
-// d f_i / d x_k over X (Alg. 3, first step); [0,0] without terms.
-template <int E>
-__device__ __forceinline__ iv eval_partial(const LTable& t, int i, int k, const Powers<E>& P) {
-  const int a = t.der_off[i * t.n + k], b = t.der_off[i * t.n + k + 1];
-  iv acc{0.0, -0.0};
-  for (int q = a; q < b; ++q) {
-    const uint64_t f = t.dfac[q];
-    const iv c = t.dco[q];
-    iv v = f ? imul(c, eval_monomial<E>(f, P)) : c;
-    acc = (q == a) ? v : iadd(acc, v);
-  }
-  return acc;
-}
-
-// Row i of J(X) into J(g, i, 0..n-1): the derivative terms of the row are
-// walked in one loop (columns ascending, each column's terms in stored order,
-// summed as eval_partial does), so the lanes of a wave, whose rows have
-// different numbers of terms per column but similar totals, run one loop of
-// about the same length instead of n loops of different lengths.
+// Row i of J(X) into J(g, i, 0..n-1) (Alg. 3, first step): d f_i / d x_k is
+// the sum of the derivative terms of entry (i, k) in stored order, the first
+// term's value being the start of the sum, and [0, 0] without terms.  The
+// derivative terms of the row are walked in one loop (columns ascending), so
+// the lanes of a wave, whose rows have different numbers of terms per column
+// but similar totals, run one loop of about the same length instead of n
+// loops of different lengths.
 template <int E, typename JV>
 __device__ __forceinline__ void eval_jacobian_row(const LTable& t, int i, const Powers<E>& P, const JV& J, int g) {
   const int n = t.n;
