@@ -1482,7 +1482,10 @@ queue_kernel(SolveArgs a) {
     }
     if (stop) break;
     if (screen) {
-      // the published boxes are read after this point, with coherent loads
+      // the published boxes are read after this point, with coherent loads;
+      // the wave has branched on the sequence words, and the compiler may not
+      // move the record loads above them
+      asm volatile("" ::: "memory");
       screen_tile<G, true>(a, T, *S, 0, 0, 0, sc, slot, full, &ql, stg);
       if (full) slot = -1;
     }
