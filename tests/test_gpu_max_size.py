@@ -49,6 +49,20 @@ def test_max_size_single_solves(gpu_ctx, cases, sched):
         assert_same(P.solve(gpu_ctx, s, schedule=sched), ref, f"{s.name} schedule {sched}")
 
 
+@pytest.mark.parametrize("variant", [{"contractor": 1}, {"inclusion": 1}, {"contractor": 1, "inclusion": 1}],
+                         ids=["krawczyk", "mean_value", "krawczyk_mean_value"])
+def test_max_size_variants(gpu_ctx, oracle_lib, variant):
+    """The Krawczyk contractor and the mean-value exclusion test at 13 and 16
+    unknowns (their kernel instances with 16-lane groups fully used)."""
+    import paper_1802_00330_amd as P
+    for n, seed in (MAX_SIZE[0], MAX_SIZE[-1]):
+        s = _case(n, seed)
+        print(f"[max-size] {s.name} n={s.n} {variant}", flush=True)
+        ref = oracle_lib.solve(s, **variant)
+        assert ref.status == 0
+        assert_same(P.solve(gpu_ctx, s, **variant), ref, f"{s.name} {variant}")
+
+
 def test_max_size_budget(gpu_ctx, cases):
     import paper_1802_00330_amd as P
     s, ref = cases[-1]
