@@ -37,25 +37,44 @@ static_assert(sizeof(SysDesc) == 128, "SysDesc size");
 constexpr int kSyncGroups = 8;
 constexpr int kSyncStride = 16;
 
+// The counters that the waves of a launch update all the time (a level's
+// pushes and claims; the work queue's claims, reservations and pending
+// count) each have a 256-byte block of their own: device-scope atomics on one
+// block are serialised at the one place where the eight XCDs meet, so
+// counters sharing a block queue behind each other's updates.
+constexpr int kHotU64 = 32;
+
 struct Ctrl {
   unsigned long long count[3];   // frontier size of level L in count[L % 3]
+  unsigned long long pad_count[kHotU64 - 3];
   unsigned long long claim[3];   // next unclaimed box of level L in claim[L % 3]
+  unsigned long long pad_claim[kHotU64 - 3];
+  // work-queue search (one system): monotone claim and reservation counters of
+  // the ring (qtail = boxes created, the budget), boxes created and not yet stepped
+  unsigned long long qhead;
+  unsigned long long pad_qhead[kHotU64 - 1];
+  unsigned long long qtail;
+  unsigned long long pad_qtail[kHotU64 - 1];
+  unsigned long long pending;
+  unsigned long long pad_pending[kHotU64 - 1];
   unsigned long long out_count;  // emitted boxes
-  unsigned long long bar;        // grid-barrier arrivals (monotone)
+  unsigned long long bar;        // grid barrier: arrivals of the last of each group (monotone)
   unsigned long long stats[8];   // processed, excluded_eval, excluded_hs, hs_skipped,
                                  // recontracted, bisected, emitted_unique, emitted_undecided
   unsigned long long levels;
   unsigned long long max_frontier;
-  // work-queue search (one system): monotone claim and reservation counters of
-  // the ring (qtail = boxes created, the budget), boxes created and not yet stepped
-  unsigned long long qhead, qtail, pending, qspare;
   int32_t status;
-  int32_t pad[7];
+  int32_t pad[39];  // the block of the other counters ends at 256 bytes
   // grid barrier of a persistent launch (zero at launch): the arrivals of each
   // group of workgroups (blockIdx % 8) and each group's release flag, each in
   // a 128-byte line of its own
   unsigned long long sync[2 * kSyncGroups * kSyncStride];
 };
+static_assert(offsetof(Ctrl, claim) == 8 * kHotU64 && offsetof(Ctrl, qhead) == 16 * kHotU64 &&
+                  offsetof(Ctrl, qtail) == 24 * kHotU64 && offsetof(Ctrl, pending) == 32 * kHotU64 &&
+                  offsetof(Ctrl, out_count) == 40 * kHotU64,
+              "hot counters of Ctrl in blocks of their own");
+static_assert(offsetof(Ctrl, sync) == 48 * kHotU64 && sizeof(Ctrl) % 256 == 0, "Ctrl lines");
 
 // Bytes of a Ctrl before its barrier lines (the counters a host reads back).
 constexpr size_t kCtrlCounterBytes = offsetof(Ctrl, sync);
