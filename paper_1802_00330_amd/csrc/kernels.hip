@@ -1339,23 +1339,13 @@ solve_kernel(SolveArgs a) {
     }
     const int cur = level & 1;
     unsigned long long* next_count = &c->count[(level + 1) % 3];
-    // A wave claims `pop` consecutive tiles per atomic: batches take it from
-    // their launch configuration; one system claims two at a level that gives
-    // every wave at least four rounds of tiles, else one (every wave of the
-    // grid claims from the level's one counter, whose atomics queue up at wide
-    // levels, while at a narrow level a second tile per claim only lengthens
-    // the level's tail).  cnt is the same for every wave, so is pop.  A wave's
+    // batches: a wave claims `pop` consecutive tiles per atomic.  A wave's
     // first claim of a level is static (the claim numbered by its global wave
     // index); later ones come from the level's counter, counted from the
     // first claim no wave holds.  A wave without a static claim touches no
     // counter, so a narrow level costs its few busy waves, not one atomic per
     // wave of the grid.
-    int pop = 1;
-    if (MULTI) {
-      if (a.tiles_per_claim > 1) pop = a.tiles_per_claim;
-    } else if (cnt >= 4ull * nwaves * (unsigned long long)W) {
-      pop = 2;
-    }
+    const int pop = (MULTI && a.tiles_per_claim > 1) ? a.tiles_per_claim : 1;
     const unsigned long long claim_w = (unsigned long long)(W * pop);
     bool first = true;
     for (;;) {
@@ -1378,21 +1368,14 @@ solve_kernel(SolveArgs a) {
         }
         continue;
       }
-      for (int t = 0; t < pop; ++t) {
-        const unsigned long long tb = base + (unsigned long long)(t * W);
-        const bool tile = tb < cnt;
-        if (tile) screen_tile<G, false>(a, T, *S, (long long)tb, (long long)cnt, cur, sc, 0, false, nullptr, stg);
-        // step the screened boxes W at a time (the ring holds 2W, so at most
-        // W - 1 wait when the next tile is screened); once the level has no
-        // tile left, all of them
-        for (;;) {
-          const unsigned long long avail = stg.tail - stg.head;
-          if (avail == 0 || (tile && avail < (unsigned long long)W)) break;
-          step_tile<G, false, false, true, VAR>(a, T, *S, J, 0, 0, cur, level, next_count, sc, 0, false, nullptr,
-                                                &stg);
-          stg.head += avail < (unsigned long long)W ? avail : (unsigned long long)W;
-        }
-        if (!tile) break;
+      if (more) screen_tile<G, false>(a, T, *S, (long long)base, (long long)cnt, cur, sc, 0, false, nullptr, stg);
+      // step the screened boxes W at a time; at the end of the level, all of them
+      for (;;) {
+        const unsigned long long avail = stg.tail - stg.head;
+        if (avail == 0 || (more && avail < (unsigned long long)W)) break;
+        step_tile<G, false, false, true, VAR>(a, T, *S, J, 0, 0, cur, level, next_count, sc, 0, false, nullptr,
+                                              &stg);
+        stg.head += avail < (unsigned long long)W ? avail : (unsigned long long)W;
       }
       if (!more) break;
     }
